@@ -1,0 +1,558 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: codes derived
+by hand from the paper's definitions (tests/golden), exact rational arithmetic,
+closed-form bounds, brute force on tiny layouts, special cases that reduce to a
+simpler scheme, and the numbers the paper prints.
+"""
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2003_02633_amd import inputs
+from tests.conftest import GOLDEN
+from tests.exact import exact_sq_norm, f32, f32_bits, nint, round_sqrt
+
+PI = math.pi
+
+
+# ---------------------------------------------------------------- golden codes
+def _golden_axis():
+    rows = []
+    with open(os.path.join(GOLDEN, "axis_codes.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            name, x, y, z, code = line.split()
+            rows.append((name, float.fromhex(x) if "p" in x else float(x), float(y), float(z),
+                         int(code, 16)))
+    return rows
+
+
+@pytest.mark.parametrize("name,x,y,z,code", _golden_axis())
+def test_axis_codes_golden(name, x, y, z, code):
+    """Hand-derived codes: field order and widths (Fig. comp_regimes c), half-up ties at
+    theta = 0 and phi = pi/2 (§2.1), exponent bias 80 and range limits (§2.3)."""
+    c = O.codec()
+    assert O.encode_one(c, f32(x), f32(y), f32(z)) == code
+
+
+def test_layout_field_positions():
+    """Fig. (comp_regimes): exponent [63:57], mantissa [56:35], n_phi [34:18], n_theta [17:0]."""
+    c = O.codec()
+    w = O.encode_one(c, 1.5, 0.0, 0.0)       # r = 1.5: e = 0, mantissa = 0.5 -> M = 2^21
+    assert (w >> 57) == 80
+    assert ((w >> 35) & ((1 << 22) - 1)) == 1 << 21
+    assert ((w >> 18) & ((1 << 17) - 1)) == 65536
+    assert (w & ((1 << 18) - 1)) == 131072
+    # the other drawn layouts: +x in <0,7,23>-17-17 and <0,8,23>-16-17
+    c2 = O.codec("0,7,23-17-17")
+    w2 = O.encode_one(c2, 1.0, 0.0, 0.0)
+    assert w2 >> 57 == 80 and ((w2 >> 17) & 0x1FFFF) == 65536 and (w2 & 0x1FFFF) == 65536
+    c3 = O.codec("0,8,23-16-17")
+    w3 = O.encode_one(c3, 1.0, 0.0, 0.0)
+    assert w3 >> 56 == 127 and ((w3 >> 17) & 0xFFFF) == 32768 and (w3 & 0x1FFFF) == 65536
+
+
+def test_nonfinite_and_zero():
+    c = O.codec()
+    for v in [(np.inf, 0, 0), (0, np.nan, 1), (1, 2, -np.inf)]:
+        assert O.encode_one(c, *v) == (127 << 57)
+    assert O.encode_one(c, 0.0, 0.0, 0.0) == 0
+    assert O.encode_one(c, -0.0, -0.0, -0.0) == 0
+    d = O.decode(c, [127 << 57])
+    assert np.isnan(d).all()
+    assert (O.decode(c, [0]) == 0).all()
+
+
+def test_signed_zero_canonical():
+    """reading: -0 is treated as +0 before the angles (theta = +pi for (-1, -0, 0))."""
+    c = O.codec()
+    assert O.encode_one(c, -1.0, -0.0, 0.0) == O.encode_one(c, -1.0, 0.0, 0.0)
+    assert O.encode_one(c, 1.0, 0.0, -0.0) == O.encode_one(c, 1.0, 0.0, 0.0)
+
+
+# ---------------------------------------------------------------- magnitude, exact
+def _rand_triples(n, seed):
+    g = np.random.default_rng(seed)
+    v = g.standard_normal((n, 3)) * (10.0 ** g.uniform(-5, 5, size=(n, 1)))
+    return v.astype(np.float32)
+
+
+def _pythagorean_ties():
+    """Vectors whose exact norm is a 24-bit odd integer times 2^k: an exact midpoint of the
+    23-bit grid, so round-to-nearest-even must decide (Euclid's formula)."""
+    out = []
+    for u in range(2900, 3000):
+        for v in (1, 2, 3, 5, 7, 11, 13, 17):
+            if math.gcd(u, v) != 1 or (u - v) % 2 == 0:
+                continue
+            a, b, cc = u * u - v * v, 2 * u * v, u * u + v * v
+            if cc % 2 == 1 and (1 << 23) <= cc < (1 << 24) and a < (1 << 24) and b < (1 << 24):
+                out.append((float(a), float(b), 0.0))
+                out.append((float(a) * 2.0 ** -30, 0.0, float(b) * 2.0 ** -30))
+    return out
+
+
+def test_magnitude_exact_rne():
+    """The magnitude field is RNE of the exact norm at 23 significant bits (reading of §2.3):
+    oracle vs exact rational arithmetic, random vectors, Pythagorean ties and float midpoints."""
+    c = O.codec()
+    cases = [tuple(map(float, r)) for r in _rand_triples(3000, 11)]
+    cases += _pythagorean_ties()
+    assert len(_pythagorean_ties()) > 10
+    # x a 24-bit odd value: exact tie alone, pushed up by a tiny second component
+    for k in range(40):
+        m = float((1 << 23) + 2 * k + 1) * 2.0 ** -23
+        cases += [(m, 0.0, 0.0), (m, 2.0 ** -60, 0.0), (m, 0.0, 2.0 ** -90), (-m, 0.0, 0.0)]
+    ties = 0
+    for (x, y, z) in cases:
+        x, y, z = f32(x), f32(y), f32(z)
+        S = exact_sq_norm(x, y, z)
+        ref = round_sqrt(S, 23)
+        r, tie = O.round_norm(x, y, z, 23, 0.0)
+        assert Fraction(r) == ref, (x, y, z)
+        ties += tie
+        w = O.encode_one(c, x, y, z)
+        E, M = w >> 57, (w >> 35) & ((1 << 22) - 1)
+        e = math.floor(math.log2(ref)) if ref > 0 else 0
+        if ref > 0 and 1 <= e + 80 <= 126:
+            # exact exponent from the rational (guard the float log2 at power-of-two edges)
+            while Fraction(2) ** e > ref:
+                e -= 1
+            while Fraction(2) ** (e + 1) <= ref:
+                e += 1
+            assert E == e + 80
+            assert Fraction(M, 1 << 22) == ref / Fraction(2) ** e - 1
+    assert ties >= 40
+
+
+def test_magnitude_ieee_special_case():
+    """With the unchanged IEEE exponent and 23 mantissa bits (<0,8,23>-16-17) the magnitude
+    field equals the single-precision bits of RN32(|x|) (special case of §2.3)."""
+    c = O.codec("0,8,23-16-17")
+    for (x, y, z) in list(_rand_triples(2000, 12)) + [(3e-39, 0, 0), (1e-44, 1e-44, 0), (2e38, 2e38, 0)]:
+        x, y, z = f32(float(x)), f32(float(y)), f32(float(z))
+        S = exact_sq_norm(x, y, z)
+        ref = round_sqrt(S, 24, Fraction(1, 1 << 149))
+        w = O.encode_one(c, x, y, z)
+        field = w >> 33
+        if ref > Fraction(3.4028234663852886e38):
+            assert field == (254 << 23) | ((1 << 23) - 1)   # saturated
+        else:
+            assert field == f32_bits(float(ref)), (x, y, z)
+
+
+def test_magnitude_range_limits():
+    """Exponent range with b_7 = 80 (§2.3; reading: E_7 = 0 zero, 127 reserved):
+    2^-79 is the smallest stored value, (2-2^-22) 2^46 the largest, beyond saturates."""
+    c = O.codec()
+    small = 2.0 ** -79
+    assert O.encode_one(c, small, 0, 0) >> 57 == 1
+    assert O.encode_one(c, 2.0 ** -80, 0, 0) == 0
+    # just below 2^-79 but rounding up to it at 23 bits stays representable
+    assert O.encode_one(c, f32(small * (1 - 2.0 ** -24)), 0, 0) >> 57 == 1
+    big = (2.0 - 2.0 ** -22) * 2.0 ** 46
+    w = O.encode_one(c, big, 0, 0)
+    assert w >> 57 == 126 and ((w >> 35) & 0x3FFFFF) == 0x3FFFFF
+    # rounds up to 2^47 -> saturates to the same code
+    assert O.encode_one(c, f32((2.0 - 2.0 ** -23) * 2.0 ** 46), 0, 0) == w
+    _, d = O.detail_one(c, 1e30, 0, 0)
+    assert d.saturated == 1
+    _, d = O.detail_one(c, 1e-30, 0, 0)
+    assert d.flushed == 1
+
+
+def test_truncation_mode_paper_literal():
+    """Paper-literal mantissa shortening (§2.3): drop d_23 of the single-precision magnitude."""
+    c = O.codec(mag_round="trunc")
+    for (x, y, z) in _rand_triples(500, 13):
+        x, y, z = float(x), float(y), float(z)
+        r32 = round_sqrt(exact_sq_norm(x, y, z), 24, Fraction(1, 1 << 149))
+        w = O.encode_one(c, x, y, z)
+        E, M = w >> 57, (w >> 35) & 0x3FFFFF
+        bits = f32_bits(float(r32))
+        if 1 <= (bits >> 23) - 47 <= 126:
+            assert E == (bits >> 23) - 47
+            assert M == (bits & 0x7FFFFF) >> 1
+
+
+# ---------------------------------------------------------------- helpers exact
+def test_exact_sign_vs_fractions():
+    g = np.random.default_rng(5)
+    for _ in range(3000):
+        k = int(g.integers(2, 8))
+        v = list(g.standard_normal(k) * 2.0 ** g.integers(-60, 60, size=k))
+        # force near-cancellation half the time
+        if g.random() < 0.5:
+            v.append(-sum(Fraction(x) for x in v).__float__())
+        exact = sum(Fraction(x) for x in v)
+        assert O.exact_sign(v) == (exact > 0) - (exact < 0)
+    assert O.exact_sign([1.0, 2.0 ** -80, -1.0]) == 1
+    assert O.exact_sign([1.0, -(2.0 ** -80), -1.0]) == -1
+    assert O.exact_sign([0.5, 0.5, -1.0]) == 0
+
+
+def test_rn32_fma_vs_fractions():
+    """One single-precision rounding of alpha*a + b, ties to even (IEEE binary32 FMA)."""
+    g = np.random.default_rng(6)
+    vals = (g.standard_normal((4000, 3)) * 2.0 ** g.integers(-20, 20, size=(4000, 3))).astype(np.float32)
+    # crafted: b chosen so that alpha*a + b lands near a float midpoint
+    for i in range(0, 4000, 4):
+        a0, al = float(vals[i, 0]), float(vals[i, 1])
+        vals[i, 2] = np.float32(-al * a0 + 1.0)
+    for al, a, b in vals:
+        al, a, b = float(al), float(a), float(b)
+        ex = Fraction(al) * Fraction(a) + Fraction(b)
+        got = O.rn32_fma(al, a, b)
+        # reference: nearest float, ties to even, by exact comparison with neighbours
+        cand = f32(float(ex))
+        best = None
+        for cnd in (cand, float(np.nextafter(np.float32(cand), np.float32(np.inf))),
+                    float(np.nextafter(np.float32(cand), np.float32(-np.inf)))):
+            d = abs(Fraction(cnd) - ex)
+            if best is None or d < best[0] or (d == best[0] and (f32_bits(cnd) & 1) == 0):
+                best = (d, cnd)
+        assert got == best[1], (al, a, b)
+
+
+# ---------------------------------------------------------------- quantisation brute force
+TINY = [(0, 3, 4, 3, 4), (0, 3, 4, 4, 5), (0, 2, 3, 2, 3)]
+
+
+def _brute_levels(u, nmax, h=lambda v: v):
+    """nearest reconstruction level in the mapped domain, ties toward the larger level
+    (round half up); levels hhat_n = 2n/nmax - 1 (Eq. a_inv written on u)."""
+    target = h(u)
+    best = None
+    for n in range(nmax + 1):
+        d = abs(target - (2.0 * n / nmax - 1.0))
+        if best is None or d < best[0] - 1e-12 or abs(d - best[0]) <= 1e-12:
+            best = (d, n)
+    return best[1]
+
+
+@pytest.mark.parametrize("fields", TINY)
+def test_quantisation_brute_force_tiny(fields):
+    """n_theta / n_phi are the nearest levels of Eq. (a_disc) (brute force over all levels)."""
+    c = O.codec(fields=fields)
+    nth_max, nph_max = O.nmax(c)
+    v = inputs.unit_sphere(4000, 21)
+    codes = O.encode(c, v)
+    _, _, nph, nth = O.fields(c, codes)
+    for i, (x, y, z) in enumerate(v.astype(np.float64)):
+        th = math.atan2(y, x)
+        ph = math.atan2(math.hypot(x, y), z)
+        assert int(nth[i]) == _brute_levels(th / math.pi, nth_max)
+        assert int(nph[i]) == _brute_levels(2 * ph / math.pi - 1, nph_max)
+
+
+def test_quantisation_rational_ties():
+    """Exact level of axis-aligned and diagonal directions from exact rationals (nint, §2.1)."""
+    c = O.codec()
+    nt, npm = O.nmax(c)
+    # theta is an exact rational multiple of pi for these directions
+    for (x, y, frac) in [(1, 0, Fraction(0)), (1, 1, Fraction(1, 4)), (0, 1, Fraction(1, 2)),
+                         (-1, 1, Fraction(3, 4)), (-1, 0, Fraction(1)), (-1, -1, Fraction(-3, 4)),
+                         (0, -1, Fraction(-1, 2)), (1, -1, Fraction(-1, 4))]:
+        w = O.encode_one(c, float(x), float(y), 0.0)
+        assert w & 0x3FFFF == nint(nt * (frac + 1) / 2)       # (theta + pi)/(2 pi) = (frac+1)/2
+        assert (w >> 18) & 0x1FFFF == nint(Fraction(npm, 2))  # phi = pi/2
+    for (rho_dir, z, frac) in [((1, 0), 1, Fraction(1, 4)), ((0, 1), -1, Fraction(3, 4))]:
+        w = O.encode_one(c, float(rho_dir[0]), float(rho_dir[1]), float(z))
+        assert (w >> 18) & 0x1FFFF == nint(npm * frac)
+
+
+# ---------------------------------------------------------------- bounds
+def _angles(v):
+    v = np.asarray(v, dtype=np.float64)
+    th = np.arctan2(v[:, 1], v[:, 0])
+    ph = np.arctan2(np.hypot(v[:, 0], v[:, 1]), v[:, 2])
+    return th, ph
+
+
+def test_angle_error_bounds():
+    """Eq. (abs_e): |eps_theta| <= pi/n_theta_max, |eps_phi| <= pi/(2 n_phi_max)."""
+    c = O.codec()
+    nt, npm = O.nmax(c)
+    v = inputs.unit_sphere(200000, 22)
+    d = O.decode64(c, O.encode(c, v))
+    th, ph = _angles(v)
+    th2, ph2 = _angles(d)
+    keep = np.hypot(v[:, 0], v[:, 1]) > 1e-3
+    dth = np.abs(np.angle(np.exp(1j * (th2 - th))))[keep]
+    dph = np.abs(ph2 - ph)
+    assert dth.max() <= PI / nt * (1 + 1e-9)
+    assert dph.max() <= PI / (2 * npm) * (1 + 1e-9)
+    # the bounds are attained (quantisation is uniform): max error within 1 % of the bound
+    assert dth.max() > 0.99 * PI / nt and dph.max() > 0.99 * PI / (2 * npm)
+
+
+def test_vector_error_bound():
+    """Eq. (v_error) first-order bound plus the magnitude rounding (2^-23) and the single-
+    precision output rounding (sqrt(3) 2^-24) bounds every normalised error."""
+    c = O.codec()
+    nt, npm = O.nmax(c)
+    eth, eph = PI / nt, PI / (2 * npm)
+    bound = math.sqrt(eth ** 2 + eph ** 2) + 2.0 ** -23 + math.sqrt(3) * 2.0 ** -24 + 1e-9
+    for v in (inputs.unit_sphere(200000, 23), inputs.sphere_loguniform(200000, 24)):
+        d = O.decode(c, O.encode(c, v)).astype(np.float64)
+        v64 = v.astype(np.float64)
+        e = np.linalg.norm(d - v64, axis=1) / np.linalg.norm(v64, axis=1)
+        assert e.max() <= bound
+
+
+# ---------------------------------------------------------------- idempotence
+def test_idempotence_sampled_full_layout():
+    """decode(encode(decode(w))) == decode(w) (near-idempotence requirement, §1) for random
+    valid codes of <0,7,22>-17-18, and codes are fixed points away from duplicate classes."""
+    c = O.codec()
+    g = np.random.default_rng(31)
+    n = 200000
+    E = g.integers(1, 127, n, dtype=np.uint64)
+    M = g.integers(0, 1 << 22, n, dtype=np.uint64)
+    P = g.integers(0, 1 << 17, n, dtype=np.uint64)
+    T = g.integers(0, 1 << 18, n, dtype=np.uint64)
+    w = (E << np.uint64(57)) | (M << np.uint64(35)) | (P << np.uint64(18)) | T
+    d1 = O.decode(c, w)
+    w2 = O.encode(c, d1)
+    d2 = O.decode(c, w2)
+    assert np.array_equal(d1, d2)
+    dup = (P == 0) | (P == (1 << 17) - 1) | (T == 0)
+    assert np.array_equal(w2[~dup], w[~dup])
+
+
+@pytest.mark.parametrize("fields", [(0, 3, 3, 3, 4), (0, 2, 4, 4, 3)])
+def test_idempotence_exhaustive_tiny(fields):
+    c = O.codec(fields=fields)
+    nbits = sum(fields)
+    w = np.arange(1 << nbits, dtype=np.uint64)
+    E = w >> np.uint64(c.m + c.p + c.t)
+    valid = E != (1 << c.e) - 1
+    w = w[valid]
+    d1 = O.decode(c, w)
+    d2 = O.decode(c, O.encode(c, d1))
+    assert np.array_equal(d1, d2)
+
+
+def test_truncation_breaks_idempotence():
+    """reading behind the RNE default: truncation drifts downward on re-encoding."""
+    c = O.codec(mag_round="trunc")
+    v = inputs.unit_sphere(100000, 32) * np.float32(3.0)
+    w1 = O.encode(c, v)
+    w2 = O.encode(c, O.decode(c, w1))
+    rate = np.mean(w1 != w2)
+    assert 0.001 < rate < 0.05
+    assert np.all(w2[w1 != w2] < w1[w1 != w2])
+
+
+# ---------------------------------------------------------------- special cases
+def test_fracsplit_power_of_two_is_plain():
+    """Eq. (q_split) with n_phi_max + 1 = 2^17: n_theta_max + 1 = 2^18 and n_p is the plain
+    bit concatenation, so codes are identical to the plain layout."""
+    c0 = O.codec()
+    c1 = O.codec(mode="frac", P=1 << 17)
+    assert O.nmax(c1) == O.nmax(c0)
+    v = inputs.sphere_loguniform(100000, 41)
+    assert np.array_equal(O.encode(c0, v), O.encode(c1, v))
+
+
+def test_fracsplit_fields_and_decode():
+    c = O.codec(mode="frac", P=163840)
+    T = O.frac_T(c)
+    assert T == (1 << 35) // 163840 and T * 163840 <= (1 << 35)
+    v = inputs.unit_sphere(50000, 42)
+    w = O.encode(c, v)
+    low = w & np.uint64((1 << 35) - 1)
+    assert (low < np.uint64(163840 * T)).all()
+    d = O.decode(c, w).astype(np.float64)
+    e = np.linalg.norm(d - v, axis=1)
+    nt, npm = O.nmax(c)
+    assert e.max() < math.hypot(PI / nt, PI / (2 * npm)) + 4e-7
+    # n_p beyond P*T is not a valid code
+    bad = np.array([(80 << 57) | (163840 * T)], dtype=np.uint64)
+    assert np.isnan(O.decode(c, bad)).all()
+
+
+def test_tanh_small_gamma_reduces_to_plain():
+    """tanh(gamma u)/tanh(gamma) -> u as gamma -> 0 (§2.5 map reduces to Eq. a_disc)."""
+    c0 = O.codec()
+    c1 = O.codec(mode="tanh", gamma=1e-4)
+    v = inputs.unit_sphere(100000, 43)
+    w0, w1 = O.encode(c0, v), O.encode(c1, v)
+    same = np.mean(w0 == w1)
+    assert same > 0.999
+    _, _, p0, t0 = O.fields(c0, w0)
+    _, _, p1, t1 = O.fields(c1, w1)
+    assert np.abs(p0.astype(np.int64) - p1.astype(np.int64)).max() <= 1
+    assert np.abs(t0.astype(np.int64) - t1.astype(np.int64)).max() <= 1
+
+
+def test_companding_endpoints_and_symmetry():
+    """The companding maps send the angle endpoints to levels 0 and n_max and the mid angle
+    to the half-up tie, like the plain map."""
+    for mode in ("tanh", "cos"):
+        c = O.codec(mode=mode)
+        c0 = O.codec()
+        for v in [(1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, 0, 1), (0, 0, -1), (0, -1, 0)]:
+            w, w0 = O.encode_one(c, *v), O.encode_one(c0, *v)
+            t, t0 = w & 0x3FFFF, w0 & 0x3FFFF
+            p, p0 = (w >> 18) & 0x1FFFF, (w0 >> 18) & 0x1FFFF
+            assert p == p0  # phi in {0, pi/2, pi}
+            if v[1] == 0 and v[2] == 0:
+                assert t == t0  # theta in {0, pi}
+
+
+# ---------------------------------------------------------------- paper statistics
+def _norm_err(c, v):
+    d = O.decode(c, O.encode(c, v)).astype(np.float64)
+    v64 = v.astype(np.float64)
+    return np.linalg.norm(d - v64, axis=1) / np.linalg.norm(v64, axis=1)
+
+
+def test_table_cpp_error_double_rows(paper):
+    """Table (C++_error), double/double rows: mean normalised error on S^2 and in [-1,1]^3."""
+    c = O.codec()
+    e = _norm_err(c, inputs.unit_sphere(1_000_000, 51))
+    sem = e.std() / math.sqrt(e.size)
+    assert abs(e.mean() - paper["dd_sphere_mean"]) < 4 * sem + 5e-10
+    assert 0.95 * paper["dd_sphere_max"] < e.max() <= paper["dd_sphere_max"] * 1.02
+    v = inputs.unit_cube(1_000_000, 52)
+    v = v[np.linalg.norm(v.astype(np.float64), axis=1) > 1e-3]
+    e = _norm_err(c, v)
+    sem = e.std() / math.sqrt(e.size)
+    assert abs(e.mean() - paper["dd_cube_mean"]) < 4 * sem + 5e-10
+
+
+def test_section23_layout_averages(paper):
+    """§2.3 averages of the three layouts on the unit ball (reading: angle-uniform sampling)."""
+    v = inputs.angle_uniform(1_000_000, 53)
+    for lay, key, tol in [("0,8,23-16-17", "avg_0_8_23_16_17", 0.005),
+                          ("0,7,23-17-17", "avg_0_7_23_17_17", 0.005),
+                          ("0,7,22-17-18", "avg_0_7_22_17_18", 0.005)]:
+        e = _norm_err(O.codec(lay), v)
+        assert abs(e.mean() / paper[key] - 1) < tol, (lay, e.mean())
+
+
+def test_radius_invariance():
+    """§2.3: the radius-normalised mean error is constant over r in [1e-8, 1e8]."""
+    c = O.codec()
+    base = inputs.unit_sphere(200000, 54).astype(np.float64)
+    means = []
+    for r in (1e-8, 1e-4, 1.0, 1e4, 1e8):
+        means.append(_norm_err(c, (base * r).astype(np.float32)).mean())
+    means = np.array(means)
+    assert means.max() / means.min() < 1.01
+
+
+def test_tanh_companding_sigma(paper):
+    """§2.5: tanh companding with gamma = 0.5 lowers sigma(e) by about 2 %."""
+    v = inputs.unit_sphere(1_000_000, 55)
+    s0 = _norm_err(O.codec(), v).std(ddof=1)
+    s1 = _norm_err(O.codec(mode="tanh", gamma=0.5), v).std(ddof=1)
+    red = 1 - s1 / s0
+    assert abs(red - paper["tanh_sigma_reduction"]) < 0.01
+
+
+def test_cos_companding_far_worse():
+    """§2.5: the cosine map gives far worse error than the uniform map."""
+    v = inputs.unit_sphere(200000, 56)
+    e0 = _norm_err(O.codec(), v)
+    e1 = _norm_err(O.codec(mode="cos"), v)
+    assert e1.mean() > 2 * e0.mean() and e1.max() > 50 * e0.max()
+
+
+def test_fracsplit_sweep_figure_ranges(paper):
+    """Fig. (frac_1718): mean and sigma over n_phi_max + 1 in [2^16, 2^18] (N = 1e4) stay in
+    the plotted ranges and vary only mildly, smallest sigma near 2^17 (§2.4)."""
+    v = inputs.unit_sphere(10000, 57)
+    Ps = [1 << 16, 90000, 1 << 17, 163840, 200000, 1 << 18]
+    mus, sds = [], []
+    for P in Ps:
+        e = _norm_err(O.codec(mode="frac", P=P), v)
+        mus.append(e.mean())
+        sds.append(e.std(ddof=1))
+    assert paper["frac_mean_lo"] < min(mus) and max(mus) < paper["frac_mean_hi"]
+    assert paper["frac_sigma_lo"] < min(sds) and max(sds) < paper["frac_sigma_hi"]
+    assert abs(int(np.argmin(sds)) - Ps.index(1 << 17)) <= 1
+
+
+def test_single_precision_bin_misses(paper):
+    """Table (C++_misses): a naive all-single-precision encoder disagrees with the exact bins
+    in a fraction of a percent of cases, never by more than one level."""
+    c = O.codec()
+    v = inputs.unit_sphere(400000, 58)
+    _, _, nph, nth = O.fields(c, O.encode(c, v))
+    x, y, z = v[:, 0], v[:, 1], v[:, 2]
+    f = np.float32
+    th = np.arctan2(y, x).astype(f)
+    r = np.sqrt(x * x + y * y + z * z).astype(f)
+    ph = np.arccos(np.clip(z / r, f(-1), f(1))).astype(f)
+    qt = np.floor(((th + f(np.pi)) * f(262143) / f(2 * np.pi)).astype(f) + f(0.5))
+    qp = np.floor((ph * f(131071) / f(np.pi)).astype(f) + f(0.5))
+    mt = np.abs(qt.astype(np.int64) - nth.astype(np.int64))
+    mp = np.abs(qp.astype(np.int64) - nph.astype(np.int64))
+    rt, rp = np.mean(mt != 0), np.mean(mp != 0)
+    assert mt.max() <= 1 and mp.max() <= 1
+    assert 0.25 * paper["miss_theta_sphere"] < rt < 4 * paper["miss_theta_sphere"]
+    assert 0.25 * paper["miss_phi_sphere"] < rp < 4 * paper["miss_phi_sphere"]
+
+
+# ---------------------------------------------------------------- reductions
+def test_dot_norm2_apply_identities():
+    """Plain definitions: norm2(a) = dot(a, a) = sum of r_hat^2 (|x_hat| = r_hat exactly in real
+    arithmetic); apply with unit rows reproduces the decoded vectors; apply is linear."""
+    c = O.codec()
+    v = inputs.sphere_loguniform(20000, 61)
+    a = O.encode(c, v)
+    b = O.encode(c, inputs.sphere_loguniform(20000, 62))
+    n2 = O.norm2(c, a)
+    assert abs(O.dot(c, a, a) - n2) <= 1e-13 * n2
+    E, M, _, _ = O.fields(c, a)
+    rhat = (1 + M.astype(np.float64) / 2 ** 22) * np.exp2(E.astype(np.float64) - 80)
+    assert abs((rhat ** 2).sum() - n2) <= 1e-12 * n2
+    d64a, d64b = O.decode64(c, a), O.decode64(c, b)
+    assert abs(O.dot(c, a, b) - float((d64a * d64b).sum())) <= 1e-12 * float(
+        (np.linalg.norm(d64a, axis=1) * np.linalg.norm(d64b, axis=1)).sum())
+    cols = 8
+    U = a[: 64 * cols].reshape(64, cols)
+    Mid = np.eye(cols, dtype=np.float32)
+    out = O.apply(c, Mid, U)
+    assert np.array_equal(out, O.decode64(c, U.reshape(-1)).reshape(64, cols, 3))
+    M1 = inputs.uniform_matrix(5, cols, 7)
+    M2 = inputs.uniform_matrix(5, cols, 8)
+    lhs = O.apply(c, (M1.astype(np.float64) + M2).astype(np.float32), U)
+    rhs = O.apply(c, M1, U) + O.apply(c, M2, U)
+    exact_sum = (M1.astype(np.float64) + M2).astype(np.float32).astype(np.float64) == (M1.astype(np.float64) + M2)
+    if exact_sum.all():
+        assert np.allclose(lhs, rhs, rtol=1e-12, atol=1e-300)
+
+
+def test_axpy_definition():
+    """Compressed c = alpha a + b (§5): decode both, one single-precision FMA per component,
+    encode; the FP64 sum of the exactly decoded operands is within the codec error of the code."""
+    c = O.codec()
+    a = O.encode(c, inputs.gaussian_with_edges(2000, 71))
+    b = O.encode(c, inputs.gaussian_with_edges(2000, 72))
+    w, c32, c64 = O.axpy(c, 0.7, a, b, want_c32=True, want_c64=True)
+    A, B = O.decode(c, a), O.decode(c, b)
+    for i in range(0, len(a), 97):
+        for k in range(3):
+            assert c32[i, k] == np.float32(O.rn32_fma(0.7, float(A[i, k]), float(B[i, k])))
+    assert np.array_equal(w, O.encode(c, c32))
+    al = float(np.float32(0.7))
+    assert np.array_equal(c64, al * O.decode64(c, a) + O.decode64(c, b))
+    # end-to-end: decoding the code of c recovers the FP64 sum within the codec error bound
+    nrm = np.linalg.norm(c64, axis=1)
+    ok = (nrm > 1e-20) & (nrm < 1e14)
+    err = np.linalg.norm(O.decode64(c, w) - c64, axis=1)[ok] / nrm[ok]
+    nt, npm = O.nmax(c)
+    bound = math.hypot(PI / nt, PI / (2 * npm)) + 2.0 ** -23
+    # plus the single-precision rounding of c32 relative to |c|
+    scale = (al * np.linalg.norm(O.decode64(c, a), axis=1) + np.linalg.norm(O.decode64(c, b), axis=1))[ok]
+    assert (err <= bound + 2 * 2.0 ** -24 * scale / nrm[ok] + 1e-12).all()
