@@ -1,0 +1,160 @@
+/*
+ * vc.h -- C ABI of libvc, the MI355X (gfx950) implementation of the inline
+ * 3-vector compression of Trojak & Witherden, "Inline Vector Compression for
+ * Computational Physics" (arXiv 2003.02633).
+ *
+ * A single-precision 3-vector (96 bits) is stored as one 64-bit code: two
+ * quantised spherical angles plus a shortened floating-point magnitude
+ * (§2.1-2.3; default layout <0,7,22>-17-18, Fig. comp_regimes c).  Encode and
+ * decode run inside streaming kernels; the paper's benchmark operation is the
+ * compressed vector addition of §5, exposed here as an axpy.
+ *
+ * Conventions for every entry point
+ *   - Pointers named d_* or documented as "device" are device (HBM) pointers
+ *     owned by the caller; the library never frees them.  Host pointers are
+ *     documented as such.
+ *   - Validation is synchronous: on any error the call returns a status and
+ *     enqueues nothing.  Kernel launches are asynchronous on `stream`
+ *     (NULL = the null stream); a launch failure returns VC_ERROR_LAUNCH.
+ *     Faults inside a kernel surface at the caller's next stream sync.
+ *   - n == 0 is a successful no-op; NULL data pointers are allowed then.
+ *   - Codes are uint64 (8-byte aligned).  Cartesian vectors are float32,
+ *     array-of-structures [n][3] (4-byte aligned; 16-byte alignment takes the
+ *     fast path).
+ *   - Non-finite input vectors encode to the reserved code (exponent field
+ *     all ones, other fields zero), which decodes to NaN.
+ *   - The library never synchronises the device implicitly, except where
+ *     documented (plan creation).
+ */
+#ifndef VC_H
+#define VC_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VC_ABI_VERSION 1
+
+typedef enum {
+  VC_SUCCESS = 0,
+  VC_ERROR_INVALID_VALUE = 1,     /* NULL pointer with n > 0, bad size or option */
+  VC_ERROR_MISALIGNED = 2,        /* code pointer not 8-byte aligned, float pointer not 4-byte aligned */
+  VC_ERROR_UNSUPPORTED_CODEC = 3, /* layout/mode combination not built into the library */
+  VC_ERROR_LAUNCH = 4,            /* kernel launch failed (hipGetLastError) */
+  VC_ERROR_HIP = 5,               /* another HIP runtime call failed */
+  VC_ERROR_OUT_OF_MEMORY = 6,     /* library-owned allocation failed */
+  VC_ERROR_OVERLAP = 7            /* output partially overlaps an input */
+} vc_status;
+
+/* bit layouts <s,e,m>-p-t of §2.2-2.3 (fields MSB->LSB: sign, exponent, mantissa, n_phi, n_theta) */
+typedef enum {
+  VC_LAYOUT_0_7_22_17_18 = 0, /* default, Fig. comp_regimes c, exponent bias 80 */
+  VC_LAYOUT_0_7_23_17_17 = 1, /* Fig. comp_regimes b, bias 80 */
+  VC_LAYOUT_0_8_23_16_17 = 2, /* Fig. comp_regimes a, IEEE exponent, bias 127 */
+  VC_LAYOUT_1_8_23_16_16 = 3  /* base scheme of §2.2: plain float32 magnitude bits above n_phi, n_theta */
+} vc_layout;
+
+/* angle discretisation: uniform (Eq. a_disc), companding maps (§2.5), fractional split (§2.4) */
+typedef enum { VC_MODE_PLAIN = 0, VC_MODE_TANH = 1, VC_MODE_COS = 2, VC_MODE_FRACSPLIT = 3 } vc_mode;
+
+/* magnitude rounding: nearest-even of the exact norm (default), or the paper-literal
+ * truncation of the single-precision magnitude's trailing mantissa bits (§2.3) */
+typedef enum { VC_MAG_RNE = 0, VC_MAG_TRUNC = 1 } vc_mag_round;
+
+enum { VC_COMPAND_PHI = 1, VC_COMPAND_THETA = 2 };
+
+/* Codec description.  Plain data, owned by the caller; build it with vc_codec_init
+ * and adjust fields before use.  struct_size versions the layout. */
+typedef struct {
+  uint32_t struct_size;   /* = sizeof(vc_codec) */
+  uint32_t layout;        /* vc_layout */
+  uint32_t mode;          /* vc_mode */
+  uint32_t mag_round;     /* vc_mag_round */
+  uint32_t compand_mask;  /* VC_COMPAND_* bits: angles a companding map applies to */
+  float gamma;            /* tanh companding parameter (§2.5), > 0 */
+  uint64_t frac_P;        /* fractional split: n_phi_max + 1 (§2.4, Eq. q_split) */
+} vc_codec;
+
+/* Fill *c with the plain codec of `layout` ("0,7,22-17-18", "0,7,23-17-17",
+ * "0,8,23-16-17", "1,8,23-16-16"; NULL selects the default <0,7,22>-17-18),
+ * RNE magnitude, companding of both angles with gamma = 0.5 when a companding mode
+ * is later selected, frac_P = 2^17.  Host-only, no device work. */
+vc_status vc_codec_init(vc_codec* c, const char* layout);
+
+/* Encode n float32 vectors (device, AoS [n][3]) into n codes (device).  §3: three
+ * single-precision numbers in, 64 bits out; angles by Eq. (a_disc) (round half up),
+ * magnitude by §2.3.  `xyz` and `codes` must not overlap. */
+vc_status vc_encode(const vc_codec* c, const float* xyz, uint64_t* codes, size_t n, hipStream_t stream);
+
+/* Decode n codes (device) into float32 vectors (device, AoS [n][3]): Eq. (a_inv) and
+ * Eq. (cart2sphere).  The zero code decodes to (0,0,0), the reserved code to NaN. */
+vc_status vc_decode(const vc_codec* c, const uint64_t* codes, float* xyz, size_t n, hipStream_t stream);
+
+/* Compressed axpy, the vector-addition kernel of §5 with a scale: for each i,
+ * c[i] = encode(alpha * decode(a[i]) + decode(b[i])), one single-precision fused
+ * multiply-add per component.  a, b, c are device code arrays of length n; c may
+ * alias a or b exactly (in-place), partial overlap returns VC_ERROR_OVERLAP. */
+vc_status vc_axpy(const vc_codec* c, float alpha, const uint64_t* a, const uint64_t* b, uint64_t* out,
+                  size_t n, hipStream_t stream);
+
+/* d_out[0] = sum_i decode(a[i]) . decode(b[i]), single-precision products with
+ * single-precision accumulation (fixed reduction order, deterministic).  d_out is
+ * one device float. */
+vc_status vc_dot(const vc_codec* c, const uint64_t* a, const uint64_t* b, size_t n, float* d_out,
+                 hipStream_t stream);
+
+/* d_out[0] = sum_i |decode(a[i])|^2, from the magnitude field alone (|x_hat| equals the
+ * stored magnitude exactly in real arithmetic), single-precision accumulation. */
+vc_status vc_norm2(const vc_codec* c, const uint64_t* a, size_t n, float* d_out, hipStream_t stream);
+
+/* Fused decode + dense apply, the operator pattern of Alg. (fr_fdiv_comp): for each
+ * element e, out[e] (rows x 3, float32) = M (rows x cols, float32 row-major, device)
+ * times decode(U[e]) (cols vectors, codes [n_elem][cols], device).  Contraction on
+ * the matrix cores in single precision with single-precision accumulation.
+ * rows <= 256, cols <= 256. */
+vc_status vc_fused_apply(const vc_codec* c, const float* M, int rows, int cols, const uint64_t* U,
+                         float* out, size_t n_elem, hipStream_t stream);
+
+/* ---- batched persistent launch over a segment table ---- */
+typedef enum { VC_OP_AXPY = 0, VC_OP_DOT = 1, VC_OP_NORM2 = 2, VC_OP_ENCODE = 3 } vc_op;
+
+/* One segment.  AXPY: out[i] = encode(alpha decode(a[i]) + decode(b[i])), codes.
+ * DOT: *(float*)out = a . b.  NORM2: *(float*)out = |a|^2.  ENCODE: a = float AoS
+ * vectors, out = codes.  All pointers are device pointers. */
+typedef struct {
+  uint32_t op;      /* vc_op */
+  float alpha;
+  uint64_t n;
+  const void* a;
+  const void* b;
+  void* out;
+} vc_segment;
+
+typedef struct vc_batch_plan vc_batch_plan;
+
+/* Build a plan for `nseg` segments (host array, copied).  Allocates the device segment
+ * table, tile table and reduction scratch, and captures one persistent kernel plus its
+ * reduction kernel into a HIP graph.  Synchronises `stream` once.  The plan owns these
+ * resources until vc_batch_plan_destroy. */
+vc_status vc_batch_plan_create(vc_batch_plan** plan, const vc_codec* c, const vc_segment* segs, int nseg,
+                               hipStream_t stream);
+/* Replay the plan's graph on `stream` (asynchronous). */
+vc_status vc_batch_plan_run(vc_batch_plan* plan, hipStream_t stream);
+/* Run the same segments as separate kernel launches, one per segment (the baseline
+ * the persistent launch is compared with). */
+vc_status vc_batch_plan_run_separate(vc_batch_plan* plan, hipStream_t stream);
+vc_status vc_batch_plan_destroy(vc_batch_plan* plan);
+
+/* Human-readable name of a status.  Static string, never NULL. */
+const char* vc_status_string(vc_status s);
+/* Library version string, static. */
+const char* vc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VC_H */

@@ -1,0 +1,47 @@
+/*
+ * vc_ext.h -- verification hooks and uncompressed reference kernels of libvc.
+ *
+ * These are not part of the method; they exist so that its kernels can be
+ * verified and measured beside uncompressed storage on the same GPU:
+ *   - vcx_axpy_dump runs the same fused axpy kernel as vc_axpy, additionally
+ *     writing the single-precision pre-encode sum (for parity checks).
+ *   - vcb_* are streaming kernels over uncompressed data: FP32 axpy
+ *     (12 bytes per 3-vector), BF16 and FP16 axpy with each 3-vector padded to
+ *     four 16-bit values (8 bytes, the same bytes as a code), and a plain copy.
+ * Conventions as in vc.h: device pointers owned by the caller, asynchronous on
+ * `stream`, synchronous validation, n == 0 is a no-op.
+ */
+#ifndef VC_EXT_H
+#define VC_EXT_H
+
+#include "vc.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Same kernel as vc_axpy; also writes c32[i][3] = alpha*decode(a[i]) + decode(b[i]) in float32
+ * (the value that was encoded).  c32 is device memory of 3n floats. */
+vc_status vcx_axpy_dump(const vc_codec* c, float alpha, const uint64_t* a, const uint64_t* b, uint64_t* out,
+                        float* c32, size_t n, hipStream_t stream);
+
+/* c[i] = alpha*a[i] + b[i] over nfloats single-precision values (3 per 3-vector, any
+ * arrangement: array-of-structures or structure-of-arrays), one FMA each. */
+vc_status vcb_axpy_f32(float alpha, const float* a, const float* b, float* c, size_t nfloats, hipStream_t stream);
+
+/* 3-vectors stored as 4 x bfloat16 (x, y, z, 0): c = alpha*a + b computed in float32 and
+ * rounded to nearest-even bfloat16.  a, b, c hold nvec*4 uint16 values (8-byte aligned). */
+vc_status vcb_axpy_bf16x4(float alpha, const uint16_t* a, const uint16_t* b, uint16_t* c, size_t nvec,
+                          hipStream_t stream);
+
+/* As vcb_axpy_bf16x4 with IEEE binary16 storage. */
+vc_status vcb_axpy_f16x4(float alpha, const uint16_t* a, const uint16_t* b, uint16_t* c, size_t nvec,
+                         hipStream_t stream);
+
+/* dst[0:bytes) = src[0:bytes): the attainable-bandwidth reference.  16-byte aligned. */
+vc_status vcb_copy(const void* src, void* dst, size_t bytes, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VC_EXT_H */

@@ -1,1 +1,256 @@
-"""MI355X-native inline 3-vector compression (arXiv 2003.02633)."""
+"""MI355X-native inline 3-vector compression (Trojak & Witherden, arXiv 2003.02633).
+
+Thin Python binding over the C ABI of ``libvc.so`` (declared in ``include/vc.h``
+and ``include/vc_ext.h``).  Every function here only marshals arguments --
+device pointers of torch tensors and the current HIP stream -- and calls the
+library; all computation runs in the library's HIP kernels.  If the library is
+not built, every call raises (there is no CPU fallback).
+
+PyTorch is used for device memory and streams only.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvc.so")
+
+VC_SUCCESS = 0
+STATUS = {0: "VC_SUCCESS", 1: "VC_ERROR_INVALID_VALUE", 2: "VC_ERROR_MISALIGNED",
+          3: "VC_ERROR_UNSUPPORTED_CODEC", 4: "VC_ERROR_LAUNCH", 5: "VC_ERROR_HIP",
+          6: "VC_ERROR_OUT_OF_MEMORY", 7: "VC_ERROR_OVERLAP"}
+LAYOUTS = {"0,7,22-17-18": 0, "0,7,23-17-17": 1, "0,8,23-16-17": 2, "1,8,23-16-16": 3}
+MODES = {"plain": 0, "tanh": 1, "cos": 2, "frac": 3}
+OPS = {"axpy": 0, "dot": 1, "norm2": 2, "encode": 3}
+
+
+class VcError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        super().__init__(f"{where}: {STATUS.get(status, status)}")
+        self.status = status
+
+
+class vc_codec(C.Structure):
+    """Mirror of ``vc_codec`` in include/vc.h."""
+    _fields_ = [("struct_size", C.c_uint32), ("layout", C.c_uint32), ("mode", C.c_uint32),
+                ("mag_round", C.c_uint32), ("compand_mask", C.c_uint32), ("gamma", C.c_float),
+                ("frac_P", C.c_uint64)]
+
+
+class vc_segment(C.Structure):
+    """Mirror of ``vc_segment`` in include/vc.h."""
+    _fields_ = [("op", C.c_uint32), ("alpha", C.c_float), ("n", C.c_uint64), ("a", C.c_void_p),
+                ("b", C.c_void_p), ("out", C.c_void_p)]
+
+
+_lib = None
+_vp = C.c_void_p
+_SIGS = {
+    "vc_codec_init": ([C.POINTER(vc_codec), C.c_char_p], C.c_int),
+    "vc_encode": ([C.POINTER(vc_codec), _vp, _vp, C.c_size_t, _vp], C.c_int),
+    "vc_decode": ([C.POINTER(vc_codec), _vp, _vp, C.c_size_t, _vp], C.c_int),
+    "vc_axpy": ([C.POINTER(vc_codec), C.c_float, _vp, _vp, _vp, C.c_size_t, _vp], C.c_int),
+    "vc_dot": ([C.POINTER(vc_codec), _vp, _vp, C.c_size_t, _vp, _vp], C.c_int),
+    "vc_norm2": ([C.POINTER(vc_codec), _vp, C.c_size_t, _vp, _vp], C.c_int),
+    "vc_fused_apply": ([C.POINTER(vc_codec), _vp, C.c_int, C.c_int, _vp, _vp, C.c_size_t, _vp], C.c_int),
+    "vc_batch_plan_create": ([C.POINTER(_vp), C.POINTER(vc_codec), C.POINTER(vc_segment), C.c_int, _vp],
+                             C.c_int),
+    "vc_batch_plan_run": ([_vp, _vp], C.c_int),
+    "vc_batch_plan_run_separate": ([_vp, _vp], C.c_int),
+    "vc_batch_plan_destroy": ([_vp], C.c_int),
+    "vc_status_string": ([C.c_int], C.c_char_p),
+    "vc_version": ([], C.c_char_p),
+    "vcx_axpy_dump": ([C.POINTER(vc_codec), C.c_float, _vp, _vp, _vp, _vp, C.c_size_t, _vp], C.c_int),
+    "vcb_axpy_f32": ([C.c_float, _vp, _vp, _vp, C.c_size_t, _vp], C.c_int),
+    "vcb_axpy_bf16x4": ([C.c_float, _vp, _vp, _vp, C.c_size_t, _vp], C.c_int),
+    "vcb_axpy_f16x4": ([C.c_float, _vp, _vp, _vp, C.c_size_t, _vp], C.c_int),
+    "vcb_copy": ([_vp, _vp, C.c_size_t, _vp], C.c_int),
+}
+
+
+def lib():
+    """Load libvc.so (built in-tree by ``python -m paper_2003_02633_amd.build``)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2003_02633_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(st: int, where: str):
+    if st != VC_SUCCESS:
+        raise VcError(st, where)
+
+
+def codec(layout: str = "0,7,22-17-18", mode: str = "plain", gamma: float = 0.5, P: int = 1 << 17,
+          compand: str = "both") -> vc_codec:
+    c = vc_codec()
+    _check(lib().vc_codec_init(C.byref(c), layout.encode()), "vc_codec_init")
+    c.mode = MODES[mode]
+    c.gamma = float(gamma)
+    c.frac_P = int(P)
+    c.compand_mask = {"both": 3, "phi": 1, "theta": 2, "none": 0}[compand]
+    return c
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream):
+    if stream is not None:
+        return C.c_void_p(int(stream))
+    return C.c_void_p(_torch().cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _require(t, dtype, what):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"{what}: expected a contiguous CUDA tensor of {dtype}")
+
+
+def vc_encode(c: vc_codec, xyz, out=None, stream=None):
+    """codes[N] (int64 holding uint64 bit patterns) of float32 vectors xyz[N, 3]."""
+    torch = _torch()
+    _require(xyz, torch.float32, "vc_encode xyz")
+    n = xyz.numel() // 3
+    if out is None:
+        out = torch.empty(n, dtype=torch.int64, device=xyz.device)
+    _require(out, torch.int64, "vc_encode out")
+    _check(lib().vc_encode(C.byref(c), _ptr(xyz), _ptr(out), n, _stream(stream)), "vc_encode")
+    return out
+
+
+def vc_decode(c: vc_codec, codes, out=None, stream=None):
+    torch = _torch()
+    _require(codes, torch.int64, "vc_decode codes")
+    n = codes.numel()
+    if out is None:
+        out = torch.empty((n, 3), dtype=torch.float32, device=codes.device)
+    _require(out, torch.float32, "vc_decode out")
+    _check(lib().vc_decode(C.byref(c), _ptr(codes), _ptr(out), n, _stream(stream)), "vc_decode")
+    return out
+
+
+def vc_axpy(c: vc_codec, alpha: float, a, b, out=None, stream=None):
+    torch = _torch()
+    _require(a, torch.int64, "vc_axpy a")
+    _require(b, torch.int64, "vc_axpy b")
+    n = a.numel()
+    if b.numel() != n:
+        raise ValueError("vc_axpy: a and b differ in length")
+    if out is None:
+        out = torch.empty_like(a)
+    _check(lib().vc_axpy(C.byref(c), float(alpha), _ptr(a), _ptr(b), _ptr(out), n, _stream(stream)), "vc_axpy")
+    return out
+
+
+def vcx_axpy_dump(c: vc_codec, alpha: float, a, b, out=None, c32=None, stream=None):
+    torch = _torch()
+    n = a.numel()
+    if out is None:
+        out = torch.empty_like(a)
+    if c32 is None:
+        c32 = torch.empty((n, 3), dtype=torch.float32, device=a.device)
+    _check(lib().vcx_axpy_dump(C.byref(c), float(alpha), _ptr(a), _ptr(b), _ptr(out), _ptr(c32), n,
+                               _stream(stream)), "vcx_axpy_dump")
+    return out, c32
+
+
+def vc_dot(c: vc_codec, a, b, out=None, stream=None):
+    torch = _torch()
+    if out is None:
+        out = torch.empty(1, dtype=torch.float32, device=a.device)
+    _check(lib().vc_dot(C.byref(c), _ptr(a), _ptr(b), a.numel(), _ptr(out), _stream(stream)), "vc_dot")
+    return out
+
+
+def vc_norm2(c: vc_codec, a, out=None, stream=None):
+    torch = _torch()
+    if out is None:
+        out = torch.empty(1, dtype=torch.float32, device=a.device)
+    _check(lib().vc_norm2(C.byref(c), _ptr(a), a.numel(), _ptr(out), _stream(stream)), "vc_norm2")
+    return out
+
+
+def vc_fused_apply(c: vc_codec, M, U, out=None, stream=None):
+    """out[e] = M @ decode(U[e]); M [rows, cols] float32, U [n_elem, cols] codes."""
+    torch = _torch()
+    _require(M, torch.float32, "vc_fused_apply M")
+    _require(U, torch.int64, "vc_fused_apply U")
+    rows, cols = M.shape
+    n_elem = U.numel() // cols
+    if out is None:
+        out = torch.empty((n_elem, rows, 3), dtype=torch.float32, device=U.device)
+    _check(lib().vc_fused_apply(C.byref(c), _ptr(M), rows, cols, _ptr(U), _ptr(out), n_elem, _stream(stream)),
+           "vc_fused_apply")
+    return out
+
+
+def vcb_axpy_f32(alpha, a, b, out=None, stream=None):
+    torch = _torch()
+    if out is None:
+        out = torch.empty_like(a)
+    _check(lib().vcb_axpy_f32(float(alpha), _ptr(a), _ptr(b), _ptr(out), a.numel(), _stream(stream)),
+           "vcb_axpy_f32")
+    return out
+
+
+def vcb_axpy_h4(kind: str, alpha, a, b, out=None, stream=None):
+    """kind 'bf16' or 'f16'; a, b: int16/uint16 tensors [N, 4]."""
+    if out is None:
+        out = _torch().empty_like(a)
+    f = lib().vcb_axpy_bf16x4 if kind == "bf16" else lib().vcb_axpy_f16x4
+    _check(f(float(alpha), _ptr(a), _ptr(b), _ptr(out), a.numel() // 4, _stream(stream)), f"vcb_axpy_{kind}x4")
+    return out
+
+
+def vcb_copy(src, dst, stream=None):
+    nbytes = src.numel() * src.element_size()
+    _check(lib().vcb_copy(_ptr(src), _ptr(dst), nbytes, _stream(stream)), "vcb_copy")
+    return dst
+
+
+class BatchPlan:
+    """Persistent batched launch over a segment table (see vc_batch_plan_create)."""
+
+    def __init__(self, c: vc_codec, segments, stream=None):
+        arr = (vc_segment * len(segments))()
+        for i, s in enumerate(segments):
+            arr[i] = vc_segment(OPS[s["op"]], float(s.get("alpha", 1.0)), int(s["n"]),
+                                s["a"].data_ptr(), s["b"].data_ptr() if s.get("b") is not None else None,
+                                s["out"].data_ptr())
+        self._keep = segments
+        self._c = c
+        self.plan = C.c_void_p()
+        _check(lib().vc_batch_plan_create(C.byref(self.plan), C.byref(c), arr, len(segments), _stream(stream)),
+               "vc_batch_plan_create")
+
+    def run(self, stream=None):
+        _check(lib().vc_batch_plan_run(self.plan, _stream(stream)), "vc_batch_plan_run")
+
+    def run_separate(self, stream=None):
+        _check(lib().vc_batch_plan_run_separate(self.plan, _stream(stream)), "vc_batch_plan_run_separate")
+
+    def close(self):
+        if self.plan:
+            lib().vc_batch_plan_destroy(self.plan)
+            self.plan = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

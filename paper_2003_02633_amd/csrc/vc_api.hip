@@ -1,0 +1,147 @@
+// vc_api.hip -- C ABI of libvc: argument validation, codec resolution, dispatch.
+#include <math.h>
+#include <string.h>
+
+#include "vc_internal.hpp"
+#include "vc_params.hpp"
+#include "../../include/vc_ext.h"
+
+namespace vc {
+
+static inline bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+static bool overlaps(const void* p, size_t pb, const void* q, size_t qb)
+{
+  uintptr_t a0 = (uintptr_t)p, a1 = a0 + pb, b0 = (uintptr_t)q, b1 = b0 + qb;
+  return a0 < b1 && b0 < a1;
+}
+
+}  // namespace vc
+
+using namespace vc;
+
+extern "C" {
+
+vc_status vc_codec_init(vc_codec* c, const char* layout)
+{
+  if (!c) return VC_ERROR_INVALID_VALUE;
+  int lay = VC_LAYOUT_0_7_22_17_18;
+  if (layout) {
+    lay = -1;
+    for (const auto& L : kLayouts)
+      if (strcmp(L.name, layout) == 0) lay = L.layout;
+    if (lay < 0) return VC_ERROR_UNSUPPORTED_CODEC;
+  }
+  memset(c, 0, sizeof(*c));
+  c->struct_size = sizeof(vc_codec);
+  c->layout = (uint32_t)lay;
+  c->mode = VC_MODE_PLAIN;
+  c->mag_round = VC_MAG_RNE;
+  c->compand_mask = VC_COMPAND_PHI | VC_COMPAND_THETA;
+  c->gamma = 0.5f;
+  c->frac_P = 1ull << 17;
+  return VC_SUCCESS;
+}
+
+vc_status vc_encode(const vc_codec* c, const float* xyz, uint64_t* codes, size_t n, hipStream_t stream)
+{
+  Resolved R;
+  vc_status st = resolve(c, &R);
+  if (st != VC_SUCCESS) return st;
+  if (n == 0) return VC_SUCCESS;
+  if (!xyz || !codes) return VC_ERROR_INVALID_VALUE;
+  if (!aligned(xyz, 4) || !aligned(codes, 8)) return VC_ERROR_MISALIGNED;
+  if (overlaps(xyz, 12 * n, codes, 8 * n)) return VC_ERROR_OVERLAP;
+  return launch_encode(R, xyz, codes, n, stream);
+}
+
+vc_status vc_decode(const vc_codec* c, const uint64_t* codes, float* xyz, size_t n, hipStream_t stream)
+{
+  Resolved R;
+  vc_status st = resolve(c, &R);
+  if (st != VC_SUCCESS) return st;
+  if (n == 0) return VC_SUCCESS;
+  if (!xyz || !codes) return VC_ERROR_INVALID_VALUE;
+  if (!aligned(xyz, 4) || !aligned(codes, 8)) return VC_ERROR_MISALIGNED;
+  if (overlaps(xyz, 12 * n, codes, 8 * n)) return VC_ERROR_OVERLAP;
+  return launch_decode(R, codes, xyz, n, stream);
+}
+
+static vc_status axpy_common(const vc_codec* c, float alpha, const uint64_t* a, const uint64_t* b, uint64_t* out,
+                             size_t n, float* dump, hipStream_t stream)
+{
+  Resolved R;
+  vc_status st = resolve(c, &R);
+  if (st != VC_SUCCESS) return st;
+  if (n == 0) return VC_SUCCESS;
+  if (!a || !b || !out) return VC_ERROR_INVALID_VALUE;
+  if (!aligned(a, 8) || !aligned(b, 8) || !aligned(out, 8)) return VC_ERROR_MISALIGNED;
+  if ((out != a && overlaps(out, 8 * n, a, 8 * n)) || (out != b && overlaps(out, 8 * n, b, 8 * n)))
+    return VC_ERROR_OVERLAP;
+  if (dump && !aligned(dump, 4)) return VC_ERROR_MISALIGNED;
+  return launch_axpy(R, alpha, a, b, out, n, dump, stream);
+}
+
+vc_status vc_axpy(const vc_codec* c, float alpha, const uint64_t* a, const uint64_t* b, uint64_t* out, size_t n,
+                  hipStream_t stream)
+{
+  return axpy_common(c, alpha, a, b, out, n, nullptr, stream);
+}
+
+vc_status vcx_axpy_dump(const vc_codec* c, float alpha, const uint64_t* a, const uint64_t* b, uint64_t* out,
+                        float* c32, size_t n, hipStream_t stream)
+{
+  if (n && !c32) return VC_ERROR_INVALID_VALUE;
+  return axpy_common(c, alpha, a, b, out, n, c32, stream);
+}
+
+static vc_status reduce_common(const vc_codec* c, const uint64_t* a, const uint64_t* b, size_t n, float* d_out,
+                               hipStream_t stream, bool is_dot)
+{
+  Resolved R;
+  vc_status st = resolve(c, &R);
+  if (st != VC_SUCCESS) return st;
+  if (!d_out) return VC_ERROR_INVALID_VALUE;
+  if (!aligned(d_out, 4)) return VC_ERROR_MISALIGNED;
+  if (n == 0) {
+    return hipMemsetAsync(d_out, 0, sizeof(float), stream) == hipSuccess ? VC_SUCCESS : VC_ERROR_HIP;
+  }
+  if (!a || (is_dot && !b)) return VC_ERROR_INVALID_VALUE;
+  if (!aligned(a, 8) || (is_dot && !aligned(b, 8))) return VC_ERROR_MISALIGNED;
+  const int np = reduce_parts(n);
+  float* parts = nullptr;
+  if (hipMallocAsync((void**)&parts, sizeof(float) * np, stream) != hipSuccess) return VC_ERROR_OUT_OF_MEMORY;
+  st = is_dot ? launch_dot(R, a, b, n, parts, np, d_out, stream) : launch_norm2(R, a, n, parts, np, d_out, stream);
+  if (hipFreeAsync(parts, stream) != hipSuccess && st == VC_SUCCESS) st = VC_ERROR_HIP;
+  return st;
+}
+
+vc_status vc_dot(const vc_codec* c, const uint64_t* a, const uint64_t* b, size_t n, float* d_out,
+                 hipStream_t stream)
+{
+  return reduce_common(c, a, b, n, d_out, stream, true);
+}
+
+vc_status vc_norm2(const vc_codec* c, const uint64_t* a, size_t n, float* d_out, hipStream_t stream)
+{
+  return reduce_common(c, a, nullptr, n, d_out, stream, false);
+}
+
+const char* vc_status_string(vc_status s)
+{
+  switch (s) {
+    case VC_SUCCESS: return "VC_SUCCESS";
+    case VC_ERROR_INVALID_VALUE: return "VC_ERROR_INVALID_VALUE";
+    case VC_ERROR_MISALIGNED: return "VC_ERROR_MISALIGNED";
+    case VC_ERROR_UNSUPPORTED_CODEC: return "VC_ERROR_UNSUPPORTED_CODEC";
+    case VC_ERROR_LAUNCH: return "VC_ERROR_LAUNCH";
+    case VC_ERROR_HIP: return "VC_ERROR_HIP";
+    case VC_ERROR_OUT_OF_MEMORY: return "VC_ERROR_OUT_OF_MEMORY";
+    case VC_ERROR_OVERLAP: return "VC_ERROR_OVERLAP";
+    default: return "VC_ERROR_UNKNOWN";
+  }
+}
+
+const char* vc_version(void) { return "libvc 0.1 (gfx950)"; }
+
+}  // extern "C"

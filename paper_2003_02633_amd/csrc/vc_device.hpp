@@ -1,0 +1,518 @@
+// vc_device.hpp -- inline single-precision codec for the MI355X kernels.
+//
+// Encodes a float32 3-vector into one 64-bit word and back, following
+// Trojak & Witherden (arXiv 2003.02633):
+//   spherical coordinates                    §2.1, Eqs. (cart2sphere, spherical)
+//   angle quantisation, round half up        §2.1, Eq. (a_disc) and the nint definition
+//   reconstruction                           §2.1, Eq. (a_inv)
+//   shortened exponent/mantissa magnitude    §2.3
+//   bit layouts <s,e,m>-p-t                  §2.3, Fig. (comp_regimes)
+//   fractional split                         §2.4, Eq. (q_split)
+//   tanh / cosine companding                 §2.5
+//
+// Design (gfx950, FP32 + integer only):
+//   * magnitude: the exact norm is rounded to nearest-even at 1+m bits.  A
+//     double-float (pairs of FP32) evaluation of x^2+y^2+z^2 and of its square
+//     root decides the rounding unless the norm lies within 2^-14 grid units of
+//     a rounding midpoint (about 3 in 10^5 vectors); those lanes take an exact
+//     128-bit integer path.
+//   * angles: both angles are atan2 problems.  Octant reduction to
+//     |b| <= tan(pi/8) (one double-float division), a short polynomial for
+//     atan(b)/b - 1, and the level coordinate carried as a double-float in
+//     level units, so the floor() of Eq. (a_disc) is taken exactly up to
+//     ~2^-24 level units -- far inside one single-precision ulp of the angle.
+//     The half-up ties of the axis directions (theta = 0, phi = pi/2) come out
+//     exactly.
+//   * decode: hardware sin/cos in revolutions (v_sin_f32 / v_cos_f32) of an
+//     exactly formed level offset; accuracy ~1e-7 of |x|.
+//
+// The header also compiles for the host (VC_HOST_EMULATION) with libm stand-ins
+// for the AMDGPU builtins, so the integer and control logic can be exercised
+// on a CPU.
+#pragma once
+
+#include <stdint.h>
+
+#ifdef VC_HOST_EMULATION
+#include <math.h>
+#include <string.h>
+#define VC_DI inline
+#define VC_NOINL
+#else
+#include <hip/hip_runtime.h>
+#define VC_DI __device__ __forceinline__
+#define VC_NOINL __device__ __noinline__
+#endif
+
+#include "vc_coeffs.inc"
+
+namespace vc {
+
+// ------------------------------------------------------------------ primitives
+#ifdef VC_HOST_EMULATION
+VC_DI uint32_t fbits(float f) { uint32_t u; memcpy(&u, &f, 4); return u; }
+VC_DI float ubits(uint32_t u) { float f; memcpy(&f, &u, 4); return f; }
+VC_DI float rsq_(float x) { return (float)(1.0 / sqrt((double)x)); }
+VC_DI float rcp_(float x) { return (float)(1.0 / (double)x); }
+VC_DI float sin_rev(float r) { return (float)sin(6.283185307179586 * (double)r); }
+VC_DI float cos_rev(float r) { return (float)cos(6.283185307179586 * (double)r); }
+VC_DI int frexp_exp(float x) { int e; frexpf(x, &e); return e; }
+VC_DI float ldexp_(float x, int e) { return ldexpf(x, e); }
+VC_DI float floor_(float x) { return floorf(x); }
+VC_DI float fma_(float a, float b, float c) { return fmaf(a, b, c); }
+VC_DI float log2_(float x) { return log2f(x); }
+VC_DI float asin_(float x) { return asinf(x); }
+#else
+VC_DI uint32_t fbits(float f) { return __float_as_uint(f); }
+VC_DI float ubits(uint32_t u) { return __uint_as_float(u); }
+VC_DI float rsq_(float x) { return __builtin_amdgcn_rsqf(x); }
+VC_DI float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
+VC_DI float sin_rev(float r) { return __builtin_amdgcn_sinf(r); }   // sin(2 pi r)
+VC_DI float cos_rev(float r) { return __builtin_amdgcn_cosf(r); }   // cos(2 pi r)
+VC_DI int frexp_exp(float x) { return __builtin_amdgcn_frexp_expf(x); }
+VC_DI float ldexp_(float x, int e) { return __builtin_amdgcn_ldexpf(x, e); }
+VC_DI float floor_(float x) { return __builtin_floorf(x); }
+VC_DI float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+VC_DI float log2_(float x) { return __builtin_amdgcn_logf(x); }     // v_log_f32 (log2)
+VC_DI float asin_(float x) { return asinf(x); }
+#endif
+VC_DI float fabs_(float x) { return ubits(fbits(x) & 0x7fffffffu); }
+VC_DI float fmax_(float a, float b) { return a > b ? a : b; }
+VC_DI float fmin_(float a, float b) { return a < b ? a : b; }
+VC_DI uint32_t umax3(uint32_t a, uint32_t b, uint32_t c) { uint32_t m = a > b ? a : b; return m > c ? m : c; }
+
+// ------------------------------------------------------------------ layouts
+// <S,E,M>-P-T with exponent bias BIAS; fields MSB->LSB: sign, exponent,
+// mantissa, n_phi, n_theta (Fig. comp_regimes).
+template <int S_, int E_, int M_, int P_, int T_, int BIAS_>
+struct Layout {
+  static constexpr int s = S_, e = E_, m = M_, p = P_, t = T_, bias = BIAS_;
+  static constexpr int sh_p = T_, sh_m = T_ + P_, sh_e = T_ + P_ + M_;
+  static constexpr uint32_t emask = (1u << E_) - 1u;
+  static constexpr int emax = (int)emask - 1;         // all-ones exponent is reserved
+  static constexpr bool keep_sub = (E_ == 8 && BIAS_ == 127);
+  static constexpr uint64_t reserved = (uint64_t)emask << sh_e;
+  static_assert(S_ + E_ + M_ + P_ + T_ == 64, "layout must fill 64 bits");
+  static_assert(M_ == 22 || M_ == 23, "mantissa of 22 or 23 bits");
+};
+using L0722 = Layout<0, 7, 22, 17, 18, 80>;
+using L0723 = Layout<0, 7, 23, 17, 17, 80>;
+using L0823 = Layout<0, 8, 23, 16, 17, 127>;
+using L1823 = Layout<1, 8, 23, 16, 16, 127>;
+
+enum Mode { PLAIN = 0, TANH = 1, COS = 2, FRAC = 3 };
+
+// Per-codec constants, filled on the host (vc_api.cpp) and passed by value.
+struct Params {
+  uint32_t nmax_t, nmax_p;   // n_theta_max, n_phi_max
+  uint32_t T;                // fractional split: n_theta_max + 1 (0 otherwise)
+  uint32_t base_t;           // theta: (n_max+1)/2 if odd, n_max/2 if even
+  uint32_t odd_t;            // 1 if n_theta_max is odd
+  uint32_t comp_t, comp_p;   // companding applied to theta / phi
+  uint32_t pad0;
+  uint64_t limit;            // fractional split: P*T (codes >= limit are invalid)
+  // encode, level units: theta |Q| = Kt |theta|/pi, phi V = Np phi/pi + 1/2
+  float Kt;                  // n_theta_max / 2
+  float Np;                  // n_phi_max
+  float Ct_h, Ct_l;          // (n_theta_max/2)/pi as a double-float
+  float Cp_h, Cp_l;          // n_phi_max/pi as a double-float
+  // decode, revolutions
+  float rt_h, rt_l;          // 1/n_theta_max as a double-float
+  float rp_h, rp_l;          // 1/(2 n_phi_max) as a double-float
+  float half_t;              // n_theta_max / 2
+  // companding
+  float gam, inv_gam, cgam;  // gamma, 1/gamma, tanh(gamma)
+  float w[8];                // tanh: h(u)/u - 1 = sum w[i] (u^2)^i (u in [-1,1])
+  int wdeg;
+};
+
+// ------------------------------------------------------------------ decode
+
+// Cartesian vector of a code: Eq. (a_inv) then Eq. (cart2sphere).
+template <class L, int MODE>
+VC_DI void decode_vec(uint64_t w, const Params& P, float& ox, float& oy, float& oz)
+{
+  const uint32_t E = (uint32_t)(w >> L::sh_e) & L::emask;
+  const uint32_t M = (uint32_t)(w >> L::sh_m) & ((1u << L::m) - 1u);
+  // magnitude (1 + M/2^m) 2^(E - b): an exact float32 bit pattern
+  uint32_t rbits;
+  if (L::keep_sub) rbits = (E << 23) | (M << (23 - L::m));                 // the IEEE value itself
+  else rbits = ((E + (uint32_t)(127 - L::bias)) << 23) | (M << (23 - L::m));
+  float r = ubits(rbits);
+  if (!L::keep_sub && E == 0) r = 0.0f;
+  if (E == L::emask) r = ubits(0x7fc00000u);                               // reserved -> NaN
+
+  uint32_t nth, nph;
+  if (MODE == FRAC) {
+    const uint64_t np = w & ((1ull << (L::p + L::t)) - 1ull);
+    if (np >= P.limit) r = ubits(0x7fc00000u);
+    // np / T by a float estimate and an exact integer correction
+    uint32_t q = (uint32_t)((float)np * rcp_((float)P.T));
+    int64_t rem = (int64_t)np - (int64_t)q * (int64_t)P.T;
+    if (rem < 0) { q -= 1; rem += P.T; }
+    if (rem >= (int64_t)P.T) { q += 1; rem -= P.T; }
+    nph = q;
+    nth = (uint32_t)rem;
+  } else {
+    nth = (uint32_t)w & ((1u << L::t) - 1u);
+    nph = (uint32_t)(w >> L::sh_p) & ((1u << L::p) - 1u);
+  }
+  // revolutions: theta_hat/(2 pi) = n/n_max - 1/2, phi_hat/(2 pi) = n/(2 n_max)
+  float rev_t, rev_p;
+  const float dt = (float)nth - P.half_t;                 // exact
+  if (MODE == TANH || MODE == COS) {
+    const float hh_t = (2.0f * (float)nth - (float)P.nmax_t) / (float)P.nmax_t;
+    const float hh_p = (2.0f * (float)nph - (float)P.nmax_p) / (float)P.nmax_p;
+    float ut = hh_t, up = hh_p;
+    if (MODE == TANH) {
+      // u = atanh(c h)/gamma = ln((1+ch)/(1-ch)) / (2 gamma)
+      if (P.comp_t) { float a = P.cgam * hh_t; ut = 0.34657359f * P.inv_gam * log2_((1.0f + a) / (1.0f - a)); }
+      if (P.comp_p) { float a = P.cgam * hh_p; up = 0.34657359f * P.inv_gam * log2_((1.0f + a) / (1.0f - a)); }
+    } else {
+      // u = (2/pi) asin(h)
+      if (P.comp_t) ut = 0.63661977f * asin_(hh_t);
+      if (P.comp_p) up = 0.63661977f * asin_(hh_p);
+    }
+    rev_t = 0.5f * ut;
+    rev_p = 0.25f * (up + 1.0f);
+    if (!P.comp_t) rev_t = fma_(dt, P.rt_h, dt * P.rt_l);
+    if (!P.comp_p) { const float fp = (float)nph; rev_p = fma_(fp, P.rp_h, fp * P.rp_l); }
+  } else {
+    rev_t = fma_(dt, P.rt_h, dt * P.rt_l);
+    const float fp = (float)nph;
+    rev_p = fma_(fp, P.rp_h, fp * P.rp_l);
+  }
+  const float st = sin_rev(rev_t), ct = cos_rev(rev_t);
+  const float sp = sin_rev(rev_p), cp = cos_rev(rev_p);
+  const float rs = r * sp;
+  ox = rs * ct;
+  oy = rs * st;
+  oz = r * cp;
+}
+
+// magnitude r_hat = |decode(w)| from the fields alone
+template <class L>
+VC_DI float decode_mag(uint64_t w)
+{
+  const uint32_t E = (uint32_t)(w >> L::sh_e) & L::emask;
+  const uint32_t M = (uint32_t)(w >> L::sh_m) & ((1u << L::m) - 1u);
+  uint32_t rbits;
+  if (L::keep_sub) rbits = (E << 23) | (M << (23 - L::m));
+  else rbits = ((E + (uint32_t)(127 - L::bias)) << 23) | (M << (23 - L::m));
+  float r = ubits(rbits);
+  if (!L::keep_sub && E == 0) r = 0.0f;
+  if (E == L::emask) r = ubits(0x7fc00000u);
+  return r;
+}
+
+// ------------------------------------------------------------------ encode helpers
+
+// Exact round-to-nearest-even of sqrt(x^2+y^2+z^2) to `prec` significant bits
+// (grid never finer than 2^-149 when keep_sub), by integer arithmetic on the
+// float bit patterns.  Returns the integer significand j and grid exponent g
+// with r_hat = j 2^g (j == 0 for the zero vector).
+VC_NOINL void exact_norm_round(float x, float y, float z, int prec, bool keep_sub, uint32_t& j_out, int& g_out)
+{
+  uint32_t Mf[3], Ef[3];
+  const float c[3] = {x, y, z};
+  int Emax = -1;
+  for (int i = 0; i < 3; i++) {
+    uint32_t u = fbits(c[i]) & 0x7fffffffu;
+    uint32_t e = u >> 23, m = u & 0x7fffffu;
+    if (e) m |= 0x800000u; else e = 1;
+    Mf[i] = m;
+    Ef[i] = e;
+    if (m && (int)e > Emax) Emax = (int)e;
+  }
+  if (Emax < 0) { j_out = 0; g_out = 0; return; }
+  // S in units of 2^(2 Emax - 300 - 64): term_i = Mf^2 << (2 (Ef - Emax) + 64)
+  unsigned __int128 S = 0;
+  bool sticky = false;
+  for (int i = 0; i < 3; i++) {
+    if (!Mf[i]) continue;
+    unsigned __int128 sq = (unsigned __int128)((uint64_t)Mf[i] * (uint64_t)Mf[i]);
+    int sh = 2 * ((int)Ef[i] - Emax) + 64;
+    if (sh >= 0) S += sq << sh;
+    else if (sh > -127) {
+      unsigned __int128 lost = sq & ((((unsigned __int128)1) << (-sh)) - 1);
+      sticky |= (lost != 0);
+      S += sq >> (-sh);
+    } else {
+      sticky = true;
+    }
+  }
+  // floor(log2 S) in absolute terms
+  int bl;
+  {
+    uint64_t hi = (uint64_t)(S >> 64), lo = (uint64_t)S;
+    bl = hi ? 128 - __builtin_clzll(hi) : (lo ? 64 - __builtin_clzll(lo) : 0);
+  }
+  const int unit = 2 * Emax - 364;                 // S_abs = S * 2^unit
+  const int l2 = bl - 1 + unit;                    // floor(log2 S_abs)
+  const int e_r = (l2 >= 0) ? l2 / 2 : -((-l2 + 1) / 2);   // floor(l2 / 2)
+  int g = e_r - (prec - 1);
+  if (keep_sub && g < -149) g = -149;
+  // T4 = floor(4 S_abs / 4^g)
+  const int sh = unit + 2 - 2 * g;
+  uint64_t T4;
+  if (sh >= 0) {
+    T4 = (uint64_t)(S << sh);
+  } else {
+    const int rs = -sh;
+    if (rs >= 128) { sticky |= (S != 0); T4 = 0; }
+    else {
+      unsigned __int128 lost = S & ((((unsigned __int128)1) << rs) - 1);
+      sticky |= (lost != 0);
+      T4 = (uint64_t)(S >> rs);
+    }
+  }
+  // s = floor(sqrt(T4)), from a float estimate plus exact integer correction
+  uint64_t s = (uint64_t)sqrtf((float)T4);
+  while (s > 0 && s * s > T4) s--;
+  while ((s + 1) * (s + 1) <= T4) s++;
+  uint64_t j = s >> 1;
+  const uint64_t m2 = (2 * j + 1) * (2 * j + 1);
+  if (T4 > m2 || (T4 == m2 && sticky)) j += 1;
+  else if (T4 == m2 && (j & 1)) j += 1;           // exact tie: to even
+  if (j >> prec) { j >>= 1; g += 1; }             // carried into the next binade
+  j_out = (uint32_t)j;
+  g_out = g;
+}
+
+// Angle of (num, den), num, den >= 0 given as double-floats, as a level
+// coordinate in double-float form:  V = B + s * C * atan(b) with the octant
+// offsets B (multiples of K/4), so that  V = K * atan2(num, den)/(pi/2) * ...
+// Concretely, with Kq = level count of a quarter turn (pi/2):
+//   atan2(num, den) in [0, pi/2] maps to [0, Kq];  C = Kq/(pi/2) (double-float).
+// Returns vh >= 0 and vl such that vh + vl = Kq * atan2(num, den)/(pi/2) when
+// den_neg == false, and 2 Kq - that value when den_neg == true.
+VC_DI void angle_levels(float num_h, float num_l, float den_h, float den_l, bool den_neg,
+                        float Kq, float C_h, float C_l, float& vh, float& vl)
+{
+  constexpr float T8 = 0.41421356237309503f;      // tan(pi/8)
+  const bool swap = num_h > den_h;
+  const float mx_h = swap ? num_h : den_h, mx_l = swap ? num_l : den_l;
+  const float mn_h = swap ? den_h : num_h, mn_l = swap ? den_l : num_l;
+  const bool R = mn_h > T8 * mx_h;
+  // reduced ratio b = mn/mx, or (mn - mx)/(mn + mx) with atan(a) = pi/4 + atan(b)
+  const float d_h = mn_h - mx_h;                  // Fast2Sum, |mx| >= |mn|
+  const float d_l = (mn_h - (d_h + mx_h)) + (mn_l - mx_l);
+  const float s_h = mx_h + mn_h;
+  const float s_l = (mn_h - (s_h - mx_h)) + (mn_l + mx_l);
+  const float nu_h = R ? d_h : mn_h, nu_l = R ? d_l : mn_l;
+  const float de_h = R ? s_h : mx_h, de_l = R ? s_l : mx_l;
+  const float rc = rcp_(fmax_(de_h, 0x1p-120f));
+  const float b0 = nu_h * rc;
+  const float b1 = (fma_(-b0, de_h, nu_h) + (nu_l - b0 * de_l)) * rc;
+  // atan(b) = b (1 + s R(s)), s = b^2
+  const float s2 = b0 * b0;
+  float Rp = VC_ATAN_R[VC_ATAN_R_DEG];
+#pragma unroll
+  for (int i = VC_ATAN_R_DEG - 1; i >= 0; i--) Rp = fma_(Rp, s2, VC_ATAN_R[i]);
+  const float u = s2 * Rp;
+  // L = C b (double-float), T = L u, H = L + T
+  const float Lh = C_h * b0;
+  const float Ll = fma_(C_h, b0, -Lh) + fma_(C_h, b1, C_l * b0);
+  const float Tt = Lh * u;
+  const float Hh = Lh + Tt;
+  const float Hl = ((Lh - Hh) + Tt) + Ll;
+  // octant offsets: atan2 = [swap] pi/2 +- ([R] pi/4 + atan b); den_neg mirrors about pi/2
+  //   !den_neg, !swap: B = R Kq/2,            s = +1
+  //   !den_neg,  swap: B = Kq - R Kq/2,       s = -1
+  //    den_neg, !swap: B = 2 Kq - R Kq/2,     s = -1
+  //    den_neg,  swap: B = Kq + R Kq/2,       s = +1
+  const bool neg = den_neg != swap;
+  const float B0 = swap ? Kq : (den_neg ? 2.0f * Kq : 0.0f);
+  const float sg = neg ? -1.0f : 1.0f;
+  const float B = R ? fma_(sg, 0.5f * Kq, B0) : B0;
+  const float sHh = sg * Hh, sHl = sg * Hl;
+  // Fast2Sum: |B| >= |H| whenever B != 0
+  vh = B + sHh;
+  vl = (sHh - (vh - B)) + sHl;
+}
+
+// floor(vh + vl + c) for vh >= 0 (exact fraction), c a small exact constant
+VC_DI int floor_dd(float vh, float vl, float c)
+{
+  const float k = floor_(vh);
+  const float f = (vh - k) + (vl + c);
+  return (int)k + (int)floor_(f);
+}
+
+// ceil(vh + vl + c) for vh >= 0
+VC_DI int ceil_dd(float vh, float vl, float c)
+{
+  const float k = floor_(vh);
+  const float f = (vh - k) + (vl + c);
+  const float ff = floor_(f);
+  return (int)k + (int)ff + (f != ff ? 1 : 0);
+}
+
+// Companding tail: h(u) = u (1 + w(u^2)); returns |Q| (1 + w) for |Q| = K |u| (double-float in/out)
+template <int MODE>
+VC_DI void compand_levels(float qh, float ql, float K, const Params& P, float& oh, float& ol)
+{
+  if (MODE == TANH) {
+    const float u = qh * (1.0f / K);
+    const float v = u * u;
+    float acc = P.w[P.wdeg];
+    for (int i = P.wdeg - 1; i >= 0; i--) acc = fma_(acc, v, P.w[i]);
+    const float d = qh * acc;                    // |Q| w, <= ~0.09 |Q|
+    oh = qh + d;
+    ol = ((qh - oh) + d) + ql * (1.0f + acc);
+  } else {
+    // cosine map: h(u) = sin(pi u/2).  Written as (pi/2) u - x^3/6 + x^5 P(x^2), x = pi u/2,
+    // with the first two terms in double-float.
+    const float PI2_h = 1.57079637f, PI2_l = -4.37113883e-08f;
+    const float inv = 1.0f / K;
+    // u = |Q|/K as double-float
+    const float uh = qh * inv;
+    const float ul = (fma_(-uh, K, qh) + ql) * inv;
+    // x = (pi/2) u
+    const float xh = PI2_h * uh;
+    const float xl = fma_(PI2_h, uh, -xh) + (PI2_h * ul + PI2_l * uh);
+    // x^2, x^3 double-float
+    const float x2h = xh * xh;
+    const float x2l = fma_(xh, xh, -x2h) + 2.0f * xh * xl;
+    const float x3h = x2h * xh;
+    const float x3l = fma_(x2h, xh, -x3h) + (x2h * xl + x2l * xh);
+    // sin x = x - x^3/6 + x^5 (1/5! - x^2/7! + x^4/9! - x^6/11! + x^8/13! - x^10/15!)
+    float t = -7.6471637e-13f;
+    t = fma_(t, x2h, 1.6059044e-10f);
+    t = fma_(t, x2h, -2.5052108e-08f);
+    t = fma_(t, x2h, 2.7557319e-06f);
+    t = fma_(t, x2h, -1.9841270e-04f);
+    t = fma_(t, x2h, 8.3333333e-03f);
+    const float x5t = x3h * x2h * t;
+    const float sixth_h = 0.166666672f, sixth_l = -4.96705388e-09f;
+    const float c3h = x3h * sixth_h;
+    const float c3l = fma_(x3h, sixth_h, -c3h) + (x3l * sixth_h + x3h * sixth_l);
+    // h = x - c3 + x5t (double-float)
+    float sh = xh - c3h;
+    float sl = ((xh - sh) - c3h) + (xl - c3l);    // |xh| >= |c3h|
+    float th = sh + x5t;
+    float tl = ((sh - th) + x5t) + sl;
+    // levels: K h
+    oh = K * th;
+    ol = fma_(K, th, -oh) + K * tl;
+  }
+}
+
+// ------------------------------------------------------------------ encode
+
+// Code of a float32 vector (the compress function of §3).
+template <class L, int MODE>
+VC_DI uint64_t encode_vec(float x, float y, float z, const Params& P)
+{
+  const uint32_t ax = fbits(x) & 0x7fffffffu, ay = fbits(y) & 0x7fffffffu, az = fbits(z) & 0x7fffffffu;
+  const uint32_t amax = umax3(ax, ay, az);
+  if (amax >= 0x7f800000u) return L::reserved;    // non-finite input
+  if (amax == 0u) return 0ull;                    // zero vector
+
+  // ---- scale so that the largest component is in [0.5, 1) (exact)
+  // amax = 1.f 2^(E-127) = 0.1f 2^(E-126): k = E - 126 (subnormal amax: k = -126)
+  const int k = (int)(amax >> 23) - 126;
+  const bool tiny = amax < 0x00800000u;           // all components subnormal: exact path only
+  const float xs = ldexp_(x, -k), ys = ldexp_(y, -k), zs = ldexp_(z, -k);
+
+  // ---- squares as double-floats
+  const float px = xs * xs, py = ys * ys, pz = zs * zs;
+  const float ex = fma_(xs, xs, -px), ey = fma_(ys, ys, -py), ez = fma_(zs, zs, -pz);
+  // rho^2 = x^2 + y^2
+  const float a1 = fmax_(px, py), b1 = fmin_(px, py);
+  const float r2h = a1 + b1;
+  const float r2l = (b1 - (r2h - a1)) + (ex + ey);
+  // S = rho^2 + z^2 (TwoSum)
+  const float Sh = r2h + pz;
+  const float bb = Sh - r2h;
+  const float Sl = ((r2h - (Sh - bb)) + (pz - bb)) + (r2l + ez);
+
+  // ---- magnitude: r = sqrt(S) as r0 + rlo, then nearest-even at 1+m bits
+  const float rS = rsq_(Sh);
+  const float r0 = Sh * rS;
+  const float rlo = (fma_(-r0, r0, Sh) + Sl) * (0.5f * rS);
+  const uint32_t b0 = fbits(r0);
+  constexpr int drop = 23 - L::m;                 // grid step in ulps of r0 is 2^drop
+  constexpr uint32_t lowm = (1u << drop) - 1u;
+  const float v = ldexp_(rlo, 150 - (int)(b0 >> 23));   // rlo in ulps of r0
+  const float pg = ((float)(b0 & lowm) + v) * (1.0f / (float)(1u << drop));
+  const float fl = floor_(pg);
+  const float fr = pg - fl;
+  const uint32_t mant = b0 & 0x7fffffu;
+  bool amb = (fabs_(fr - 0.5f) < 0x1p-14f) || (mant < 8u) || (mant > 0x7ffff7u) || tiny;
+  const int jg = (int)fl + (fr > 0.5f ? 1 : 0);
+  uint32_t rb = (b0 & ~lowm) + ((uint32_t)jg << drop);
+  int e_r = (int)(rb >> 23) - 127 + k;            // unbiased exponent of r_hat
+  uint32_t Mfield = (rb & 0x7fffffu) >> drop;
+  if (L::keep_sub) amb = amb || (e_r + L::bias <= 1);
+  if (amb) {
+    uint32_t j;
+    int g;
+    exact_norm_round(x, y, z, L::m + 1, L::keep_sub, j, g);
+    if (j >= (1u << L::m)) {                      // normal
+      e_r = g + L::m;
+      Mfield = j - (1u << L::m);
+    } else {                                      // subnormal (keep_sub only)
+      e_r = -L::bias;                             // -> E = 0
+      Mfield = j;
+    }
+  }
+  int E = e_r + L::bias;
+  if (E < 1 && !(L::keep_sub && E == 0)) return 0ull;   // underflow flushes to the zero code
+  if (L::keep_sub && E == 0 && Mfield == 0u) return 0ull;
+  if (E > L::emax) { E = L::emax; Mfield = (1u << L::m) - 1u; }   // saturate
+
+  // ---- rho = sqrt(x^2 + y^2) as a double-float (for phi)
+  const float rr = rsq_(fmax_(r2h, 0x1p-100f));
+  const float rho_h = r2h * rr;
+  const float rho_l = (fma_(-rho_h, rho_h, r2h) + r2l) * (0.5f * rr);
+
+  // ---- theta = atan2(y, x) on |Q| = Kt |theta|/pi  (Kq = Kt/2 levels per quarter turn)
+  float qh, ql;
+  // signs from the unscaled inputs (a tiny component may underflow to -0 when scaled)
+  const bool yneg = y < 0.0f, xneg = x < 0.0f, zneg = z < 0.0f;
+  angle_levels(fabs_(ys), 0.0f, fabs_(xs), 0.0f, xneg, 0.5f * P.Kt, P.Ct_h, P.Ct_l, qh, ql);
+  if (MODE == TANH || MODE == COS) { if (P.comp_t) compand_levels<MODE>(qh, ql, P.Kt, P, qh, ql); }
+  uint32_t nth;
+  if (MODE == FRAC && !P.odd_t) {
+    // even n_theta_max: n = n_max/2 + floor(Q + 1/2), Q = +-|Q|
+    nth = yneg ? (uint32_t)((int)P.base_t - ceil_dd(qh, ql, -0.5f))
+                      : (uint32_t)((int)P.base_t + floor_dd(qh, ql, 0.5f));
+  } else {
+    // odd n_theta_max: n = (n_max+1)/2 + floor(Q); for y < 0, |Q| is never an integer
+    const int f = floor_dd(qh, ql, 0.0f);
+    nth = yneg ? (uint32_t)((int)P.base_t - 1 - f) : (uint32_t)((int)P.base_t + f);
+  }
+
+  // ---- phi = atan2(rho, z): V = n_phi_max phi/pi + 1/2, n = floor(V)  (Kq = Np/2)
+  float vh, vl;
+  angle_levels(rho_h, rho_l, fabs_(zs), 0.0f, zneg, 0.5f * P.Np, P.Cp_h, P.Cp_l, vh, vl);
+  uint32_t nph;
+  if ((MODE == TANH || MODE == COS) && P.comp_p) {
+    // centred coordinate Qc = V - 1/2 - Np/2 = (Np/2) u_phi; tie at phi = pi/2 (z == 0)
+    const float Kc = 0.5f * P.Np;
+    float ch = vh - Kc;                           // exact when vh in [Kc/2, 2 Kc]; else via Fast2Sum
+    float cl;
+    {
+      const float big = fabs_(vh) >= Kc ? vh : -Kc, sml = fabs_(vh) >= Kc ? -Kc : vh;
+      cl = (sml - (ch - big)) + vl;
+    }
+    const bool negc = ch < 0.0f || (ch == 0.0f && cl < 0.0f);
+    float mh = negc ? -ch : ch, ml = negc ? -cl : cl;
+    compand_levels<MODE>(mh, ml, Kc, P, mh, ml);
+    const int base_p = (int)((P.nmax_p + 1u) / 2u);
+    const int f = floor_dd(mh, ml, 0.0f);
+    nph = negc ? (uint32_t)(base_p - 1 - f) : (uint32_t)(base_p + f);
+    if (z == 0.0f) nph = (uint32_t)base_p;
+  } else {
+    nph = (uint32_t)floor_dd(vh, vl, 0.5f);
+  }
+
+  // ---- pack: [s][E][M][n_phi][n_theta]  (Eq. q_split for the fractional split)
+  uint64_t low;
+  if (MODE == FRAC) low = (uint64_t)nph * (uint64_t)P.T + (uint64_t)nth;
+  else low = ((uint64_t)nph << L::t) | (uint64_t)nth;
+  return ((uint64_t)(uint32_t)E << L::sh_e) | ((uint64_t)Mfield << L::sh_m) | low;
+}
+
+}  // namespace vc

@@ -1,0 +1,38 @@
+// vc_internal.hpp -- host-side declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/vc.h"
+#include "vc_device.hpp"
+#include "vc_params.hpp"
+
+namespace vc {
+
+// tuning knobs of the streaming kernels (autotuned; see tune.cpp)
+struct StreamCfg {
+  int block;       // threads per block
+  int vpt;         // vectors per thread and iteration
+  int nt;          // non-temporal loads/stores
+};
+StreamCfg stream_cfg(int op, size_t n);
+
+vc_status launch_encode(const Resolved& R, const float* xyz, uint64_t* codes, size_t n, hipStream_t s);
+vc_status launch_decode(const Resolved& R, const uint64_t* codes, float* xyz, size_t n, hipStream_t s);
+vc_status launch_axpy(const Resolved& R, float alpha, const uint64_t* a, const uint64_t* b, uint64_t* c,
+                      size_t n, float* c32_dump, hipStream_t s);
+vc_status launch_dot(const Resolved& R, const uint64_t* a, const uint64_t* b, size_t n, float* partials,
+                     int nparts, float* d_out, hipStream_t s);
+vc_status launch_norm2(const Resolved& R, const uint64_t* a, size_t n, float* partials, int nparts,
+                       float* d_out, hipStream_t s);
+int reduce_parts(size_t n);
+
+inline vc_status launch_status()
+{
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? VC_SUCCESS : VC_ERROR_LAUNCH;
+}
+
+}  // namespace vc

@@ -1,0 +1,163 @@
+// vc_params.hpp -- host-side resolution of a vc_codec into the kernels' constants.
+// Host-only C++ (no device code); included by the C ABI and by the CPU emulation
+// build of the codec.
+#pragma once
+
+#include <math.h>
+#include <string.h>
+
+#include "../../include/vc.h"
+#include "vc_device.hpp"
+
+namespace vc {
+
+// Resolved codec: compile-time layout/mode ids plus the runtime constants.
+struct Resolved {
+  int layout;      // vc_layout
+  int mode;        // vc::Mode
+  int mag_round;   // vc_mag_round
+  Params P;
+};
+
+static const struct {
+  const char* name;
+  int layout;
+} kLayouts[] = {
+    {"0,7,22-17-18", VC_LAYOUT_0_7_22_17_18},
+    {"0,7,23-17-17", VC_LAYOUT_0_7_23_17_17},
+    {"0,8,23-16-17", VC_LAYOUT_0_8_23_16_17},
+    {"1,8,23-16-16", VC_LAYOUT_1_8_23_16_16},
+};
+
+struct LayoutBits {
+  int e, m, p, t, bias;
+};
+static inline LayoutBits layout_bits(int layout)
+{
+  switch (layout) {
+    case VC_LAYOUT_0_7_22_17_18: return {7, 22, 17, 18, 80};
+    case VC_LAYOUT_0_7_23_17_17: return {7, 23, 17, 17, 80};
+    case VC_LAYOUT_0_8_23_16_17: return {8, 23, 16, 17, 127};
+    default: return {8, 23, 16, 16, 127};
+  }
+}
+
+static inline void split_dd(long double v, float* hi, float* lo)
+{
+  float h = (float)v;
+  *hi = h;
+  *lo = (float)(v - (long double)h);
+}
+
+// Least-squares fit (Chebyshev nodes) of w(v) = tanh(gamma sqrt v)/(tanh(gamma) sqrt v) - 1 on
+// v in [0, 1]; returns the max residual of the float32 coefficients.
+static inline double fit_tanh_tail(double gamma, float* w, int deg)
+{
+  const int N = 400;
+  const int D = deg + 1;
+  long double A[16][16] = {{0}}, rhs[16] = {0};
+  const long double c = tanhl((long double)gamma);
+  for (int k = 0; k < N; k++) {
+    long double v = 0.5L + 0.5L * cosl(3.14159265358979323846264338327950288L * (k + 0.5L) / N);
+    long double u = sqrtl(v);
+    long double f = (u < 1e-6L) ? (gamma / c) * (1.0L - gamma * gamma * v / 3.0L) - 1.0L
+                                : tanhl(gamma * u) / (c * u) - 1.0L;
+    long double pw[16];
+    pw[0] = 1.0L;
+    for (int i = 1; i < D; i++) pw[i] = pw[i - 1] * v;
+    for (int i = 0; i < D; i++) {
+      rhs[i] += pw[i] * f;
+      for (int j = 0; j < D; j++) A[i][j] += pw[i] * pw[j];
+    }
+  }
+  // Gaussian elimination with partial pivoting
+  for (int i = 0; i < D; i++) {
+    int piv = i;
+    for (int r = i + 1; r < D; r++)
+      if (fabsl(A[r][i]) > fabsl(A[piv][i])) piv = r;
+    for (int j = 0; j < D; j++) { long double t = A[i][j]; A[i][j] = A[piv][j]; A[piv][j] = t; }
+    { long double t = rhs[i]; rhs[i] = rhs[piv]; rhs[piv] = t; }
+    for (int r = i + 1; r < D; r++) {
+      long double f = A[r][i] / A[i][i];
+      for (int j = i; j < D; j++) A[r][j] -= f * A[i][j];
+      rhs[r] -= f * rhs[i];
+    }
+  }
+  long double coef[16];
+  for (int i = D - 1; i >= 0; i--) {
+    long double s = rhs[i];
+    for (int j = i + 1; j < D; j++) s -= A[i][j] * coef[j];
+    coef[i] = s / A[i][i];
+  }
+  for (int i = 0; i < D; i++) w[i] = (float)coef[i];
+  double maxerr = 0.0;
+  for (int k = 0; k <= 2000; k++) {
+    double u = k / 2000.0, v = u * u;
+    double f = (u < 1e-6) ? (gamma / (double)c) - 1.0 : tanh(gamma * u) / ((double)c * u) - 1.0;
+    double acc = w[deg];
+    for (int i = deg - 1; i >= 0; i--) acc = acc * v + w[i];
+    double e = fabs(acc - f);
+    if (e > maxerr) maxerr = e;
+  }
+  return maxerr;
+}
+
+inline vc_status resolve(const vc_codec* c, Resolved* R)
+{
+  if (!c || !R) return VC_ERROR_INVALID_VALUE;
+  if (c->struct_size != sizeof(vc_codec)) return VC_ERROR_INVALID_VALUE;
+  if (c->layout > VC_LAYOUT_1_8_23_16_16) return VC_ERROR_UNSUPPORTED_CODEC;
+  if (c->mode > VC_MODE_FRACSPLIT) return VC_ERROR_UNSUPPORTED_CODEC;
+  if (c->mag_round != VC_MAG_RNE) return VC_ERROR_UNSUPPORTED_CODEC;   // truncation: oracle-only
+  if (c->mode != VC_MODE_PLAIN && c->layout != VC_LAYOUT_0_7_22_17_18) return VC_ERROR_UNSUPPORTED_CODEC;
+  memset(R, 0, sizeof(*R));
+  R->layout = (int)c->layout;
+  R->mode = (int)c->mode;
+  R->mag_round = (int)c->mag_round;
+  Params& P = R->P;
+  const LayoutBits lb = layout_bits((int)c->layout);
+  uint64_t nt, np;
+  if (c->mode == VC_MODE_FRACSPLIT) {
+    const uint64_t cap = 1ull << (lb.p + lb.t);
+    if (c->frac_P < 2 || c->frac_P >= cap / 2) return VC_ERROR_INVALID_VALUE;
+    const uint64_t T = cap / c->frac_P;        // largest T with P T <= 2^(p+t)  (Eq. q_split)
+    if (T < 2 || T > (1ull << 24) || c->frac_P > (1ull << 24)) return VC_ERROR_UNSUPPORTED_CODEC;
+    nt = T - 1;
+    np = c->frac_P - 1;
+    P.T = (uint32_t)T;
+    P.limit = c->frac_P * T;
+  } else {
+    nt = (1ull << lb.t) - 1;
+    np = (1ull << lb.p) - 1;
+    P.T = (uint32_t)(nt + 1);
+    P.limit = ~0ull;
+  }
+  P.nmax_t = (uint32_t)nt;
+  P.nmax_p = (uint32_t)np;
+  P.odd_t = (uint32_t)(nt & 1);
+  P.base_t = (uint32_t)((nt & 1) ? (nt + 1) / 2 : nt / 2);
+  P.Kt = (float)((double)nt / 2.0);
+  P.Np = (float)np;
+  P.half_t = P.Kt;
+  const long double PI = 3.14159265358979323846264338327950288L;
+  split_dd((long double)nt / 2.0L / PI, &P.Ct_h, &P.Ct_l);
+  split_dd((long double)np / PI, &P.Cp_h, &P.Cp_l);
+  split_dd(1.0L / (long double)nt, &P.rt_h, &P.rt_l);
+  split_dd(1.0L / (2.0L * (long double)np), &P.rp_h, &P.rp_l);
+  if (c->mode == VC_MODE_TANH || c->mode == VC_MODE_COS) {
+    P.comp_t = (c->compand_mask & VC_COMPAND_THETA) ? 1u : 0u;
+    P.comp_p = (c->compand_mask & VC_COMPAND_PHI) ? 1u : 0u;
+  }
+  if (c->mode == VC_MODE_TANH) {
+    if (!(c->gamma > 0.0f) || c->gamma > 1.5f) return VC_ERROR_UNSUPPORTED_CODEC;
+    P.gam = c->gamma;
+    P.inv_gam = 1.0f / c->gamma;
+    P.cgam = (float)tanh((double)c->gamma);
+    P.wdeg = 7;
+    const double err = fit_tanh_tail((double)c->gamma, P.w, P.wdeg);
+    if (err > 2e-8) return VC_ERROR_UNSUPPORTED_CODEC;   // residual relative to |Q| scales like the 1-ulp window
+  }
+  return VC_SUCCESS;
+}
+
+}  // namespace vc

@@ -1,0 +1,337 @@
+// vc_stream.hip -- streaming kernels over compressed 3-vectors (gfx950).
+//
+// Every kernel is a memory stream: each wavefront reads and writes contiguous
+// 1 KiB (or 3 KiB for float32 AoS) spans with 16-byte global loads/stores, and
+// the whole codec (decode / FMA / encode) runs in registers between them.
+//   k_axpy   : c = encode(alpha decode(a) + decode(b))    -- the C = A + B kernel of §5
+//   k_encode : float32 AoS -> codes                        -- compress(), §3
+//   k_decode : codes -> float32 AoS                        -- decompress(), Alg. (fr_fdiv_comp)
+//   k_dot / k_norm2 : FP32 reductions over decoded vectors
+#include "vc_internal.hpp"
+
+namespace vc {
+
+typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <bool NT, class T>
+__device__ __forceinline__ T ld(const T* p)
+{
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+template <bool NT, class T>
+__device__ __forceinline__ void st(T* p, T v)
+{
+  if constexpr (NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
+// ------------------------------------------------------------------ axpy
+// Each lane handles U pairs of consecutive codes per grid step; pair u of a
+// block lives at [blk + u*2*BS + 2*tid, +2), so every load/store instruction of
+// a wave covers 1 KiB contiguous.
+template <class L, int MODE, int BS, int U, bool NT, bool DUMP>
+__global__ __launch_bounds__(BS) void k_axpy(const uint64_t* __restrict__ a, const uint64_t* __restrict__ b,
+                                             uint64_t* __restrict__ c, size_t n, size_t ntiles, float alpha,
+                                             Params P, float* __restrict__ dump)
+{
+  // tiles [0, ntiles) take the 16-byte path (pointers 16-byte aligned); the rest is scalar
+  constexpr size_t TILE = (size_t)2 * BS * U;
+  for (size_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const size_t base = tile * TILE + 2 * threadIdx.x;
+    u64x2 va[U], vb[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      va[u] = ld<NT>((const u64x2*)(a + base + (size_t)u * 2 * BS));
+      vb[u] = ld<NT>((const u64x2*)(b + base + (size_t)u * 2 * BS));
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      u64x2 out;
+#pragma unroll
+      for (int h = 0; h < 2; h++) {
+        float ax, ay, az, bx, by, bz;
+        decode_vec<L, MODE>(va[u][h], P, ax, ay, az);
+        decode_vec<L, MODE>(vb[u][h], P, bx, by, bz);
+        const float cx = __builtin_fmaf(alpha, ax, bx);
+        const float cy = __builtin_fmaf(alpha, ay, by);
+        const float cz = __builtin_fmaf(alpha, az, bz);
+        if constexpr (DUMP) {
+          const size_t i = base + (size_t)u * 2 * BS + h;
+          dump[3 * i] = cx; dump[3 * i + 1] = cy; dump[3 * i + 2] = cz;
+        }
+        out[h] = encode_vec<L, MODE>(cx, cy, cz, P);
+      }
+      st<NT>((u64x2*)(c + base + (size_t)u * 2 * BS), out);
+    }
+  }
+  // tail: vectors from ntiles*TILE on, one per thread
+  const size_t start = ntiles * TILE;
+  for (size_t i = start + (size_t)blockIdx.x * BS + threadIdx.x; i < n; i += (size_t)gridDim.x * BS) {
+    float ax, ay, az, bx, by, bz;
+    decode_vec<L, MODE>(a[i], P, ax, ay, az);
+    decode_vec<L, MODE>(b[i], P, bx, by, bz);
+    const float cx = __builtin_fmaf(alpha, ax, bx);
+    const float cy = __builtin_fmaf(alpha, ay, by);
+    const float cz = __builtin_fmaf(alpha, az, bz);
+    if constexpr (DUMP) { dump[3 * i] = cx; dump[3 * i + 1] = cy; dump[3 * i + 2] = cz; }
+    c[i] = encode_vec<L, MODE>(cx, cy, cz, P);
+  }
+}
+
+// ------------------------------------------------------------------ encode / decode
+// Groups of 4 vectors per lane: 48 bytes of float32 AoS (3 x 16-byte accesses)
+// and 32 bytes of codes (2 x 16-byte accesses).  Requires 16-byte aligned
+// pointers (checked by the launcher, which otherwise uses the scalar kernel).
+template <class L, int MODE, int BS, bool NT>
+__global__ __launch_bounds__(BS) void k_encode4(const float* __restrict__ xyz, uint64_t* __restrict__ codes,
+                                                size_t n, Params P)
+{
+  const size_t ng = n / 4;
+  for (size_t g = (size_t)blockIdx.x * BS + threadIdx.x; g < ng; g += (size_t)gridDim.x * BS) {
+    const f32x4* src = (const f32x4*)(xyz + 12 * g);
+    const f32x4 q0 = ld<NT>(src), q1 = ld<NT>(src + 1), q2 = ld<NT>(src + 2);
+    u64x2 o0, o1;
+    o0[0] = encode_vec<L, MODE>(q0[0], q0[1], q0[2], P);
+    o0[1] = encode_vec<L, MODE>(q0[3], q1[0], q1[1], P);
+    o1[0] = encode_vec<L, MODE>(q1[2], q1[3], q2[0], P);
+    o1[1] = encode_vec<L, MODE>(q2[1], q2[2], q2[3], P);
+    u64x2* dst = (u64x2*)(codes + 4 * g);
+    st<NT>(dst, o0);
+    st<NT>(dst + 1, o1);
+  }
+  for (size_t i = 4 * ng + (size_t)blockIdx.x * BS + threadIdx.x; i < n; i += (size_t)gridDim.x * BS)
+    codes[i] = encode_vec<L, MODE>(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], P);
+}
+
+template <class L, int MODE, int BS>
+__global__ __launch_bounds__(BS) void k_encode1(const float* __restrict__ xyz, uint64_t* __restrict__ codes,
+                                                size_t n, Params P)
+{
+  for (size_t i = (size_t)blockIdx.x * BS + threadIdx.x; i < n; i += (size_t)gridDim.x * BS)
+    codes[i] = encode_vec<L, MODE>(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], P);
+}
+
+template <class L, int MODE, int BS, bool NT>
+__global__ __launch_bounds__(BS) void k_decode4(const uint64_t* __restrict__ codes, float* __restrict__ xyz,
+                                                size_t n, Params P)
+{
+  const size_t ng = n / 4;
+  for (size_t g = (size_t)blockIdx.x * BS + threadIdx.x; g < ng; g += (size_t)gridDim.x * BS) {
+    const u64x2* src = (const u64x2*)(codes + 4 * g);
+    const u64x2 w0 = ld<NT>(src), w1 = ld<NT>(src + 1);
+    float v[12];
+    decode_vec<L, MODE>(w0[0], P, v[0], v[1], v[2]);
+    decode_vec<L, MODE>(w0[1], P, v[3], v[4], v[5]);
+    decode_vec<L, MODE>(w1[0], P, v[6], v[7], v[8]);
+    decode_vec<L, MODE>(w1[1], P, v[9], v[10], v[11]);
+    f32x4* dst = (f32x4*)(xyz + 12 * g);
+    st<NT>(dst, f32x4{v[0], v[1], v[2], v[3]});
+    st<NT>(dst + 1, f32x4{v[4], v[5], v[6], v[7]});
+    st<NT>(dst + 2, f32x4{v[8], v[9], v[10], v[11]});
+  }
+  for (size_t i = 4 * ng + (size_t)blockIdx.x * BS + threadIdx.x; i < n; i += (size_t)gridDim.x * BS)
+    decode_vec<L, MODE>(codes[i], P, xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2]);
+}
+
+template <class L, int MODE, int BS>
+__global__ __launch_bounds__(BS) void k_decode1(const uint64_t* __restrict__ codes, float* __restrict__ xyz,
+                                                size_t n, Params P)
+{
+  for (size_t i = (size_t)blockIdx.x * BS + threadIdx.x; i < n; i += (size_t)gridDim.x * BS)
+    decode_vec<L, MODE>(codes[i], P, xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2]);
+}
+
+// ------------------------------------------------------------------ reductions
+template <int BS>
+__device__ __forceinline__ float block_sum(float v)
+{
+  __shared__ float red[BS / 64];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  float s = 0.0f;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < BS / 64; i++) s += red[i];
+  }
+  return s;
+}
+
+template <class L, int MODE, int BS>
+__global__ __launch_bounds__(BS) void k_dot(const uint64_t* __restrict__ a, const uint64_t* __restrict__ b,
+                                            size_t n, Params P, float* __restrict__ parts)
+{
+  float acc = 0.0f;
+  for (size_t i = (size_t)blockIdx.x * BS + threadIdx.x; i < n; i += (size_t)gridDim.x * BS) {
+    float ax, ay, az, bx, by, bz;
+    decode_vec<L, MODE>(a[i], P, ax, ay, az);
+    decode_vec<L, MODE>(b[i], P, bx, by, bz);
+    acc = __builtin_fmaf(ax, bx, acc);
+    acc = __builtin_fmaf(ay, by, acc);
+    acc = __builtin_fmaf(az, bz, acc);
+  }
+  const float s = block_sum<BS>(acc);
+  if (threadIdx.x == 0) parts[blockIdx.x] = s;
+}
+
+template <class L, int BS>
+__global__ __launch_bounds__(BS) void k_norm2(const uint64_t* __restrict__ a, size_t n, float* __restrict__ parts)
+{
+  float acc = 0.0f;
+  for (size_t i = (size_t)blockIdx.x * BS + threadIdx.x; i < n; i += (size_t)gridDim.x * BS) {
+    const float r = decode_mag<L>(a[i]);
+    acc = __builtin_fmaf(r, r, acc);
+  }
+  const float s = block_sum<BS>(acc);
+  if (threadIdx.x == 0) parts[blockIdx.x] = s;
+}
+
+// fixed-order final sum of the per-block partials (deterministic)
+__global__ __launch_bounds__(256) void k_reduce_parts(const float* __restrict__ parts, int nparts,
+                                                      float* __restrict__ out)
+{
+  float acc = 0.0f;
+  for (int i = threadIdx.x; i < nparts; i += 256) acc += parts[i];
+  const float s = block_sum<256>(acc);
+  if (threadIdx.x == 0) out[0] = s;
+}
+
+// ------------------------------------------------------------------ launchers
+static inline unsigned grid_for(size_t work, size_t per_block, unsigned cap)
+{
+  size_t g = (work + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (unsigned)g;
+}
+
+template <class L, int MODE>
+static vc_status axpy_t(const Resolved& R, float alpha, const uint64_t* a, const uint64_t* b, uint64_t* c,
+                        size_t n, float* dump, hipStream_t s)
+{
+  constexpr int BS = 256, U = 1;
+  constexpr size_t TILE = (size_t)2 * BS * U;
+  const bool aligned = (((uintptr_t)a | (uintptr_t)b | (uintptr_t)c) & 15u) == 0;
+  const size_t ntiles = aligned ? n / TILE : 0;
+  const unsigned grid = grid_for(n, TILE, 1u << 30);
+  if (dump)
+    hipLaunchKernelGGL((k_axpy<L, MODE, BS, U, false, true>), dim3(grid), dim3(BS), 0, s, a, b, c, n, ntiles,
+                       alpha, R.P, dump);
+  else
+    hipLaunchKernelGGL((k_axpy<L, MODE, BS, U, true, false>), dim3(grid), dim3(BS), 0, s, a, b, c, n, ntiles,
+                       alpha, R.P, dump);
+  return launch_status();
+}
+
+template <class L, int MODE>
+static vc_status encode_t(const Resolved& R, const float* xyz, uint64_t* codes, size_t n, hipStream_t s)
+{
+  constexpr int BS = 256;
+  const bool aligned = (((uintptr_t)xyz | (uintptr_t)codes) & 15u) == 0;
+  if (aligned) {
+    const unsigned grid = grid_for(n, (size_t)4 * BS, 1u << 30);
+    hipLaunchKernelGGL((k_encode4<L, MODE, BS, true>), dim3(grid), dim3(BS), 0, s, xyz, codes, n, R.P);
+  } else {
+    const unsigned grid = grid_for(n, (size_t)BS, 1u << 30);
+    hipLaunchKernelGGL((k_encode1<L, MODE, BS>), dim3(grid), dim3(BS), 0, s, xyz, codes, n, R.P);
+  }
+  return launch_status();
+}
+
+template <class L, int MODE>
+static vc_status decode_t(const Resolved& R, const uint64_t* codes, float* xyz, size_t n, hipStream_t s)
+{
+  constexpr int BS = 256;
+  const bool aligned = (((uintptr_t)xyz | (uintptr_t)codes) & 15u) == 0;
+  if (aligned) {
+    const unsigned grid = grid_for(n, (size_t)4 * BS, 1u << 30);
+    hipLaunchKernelGGL((k_decode4<L, MODE, BS, true>), dim3(grid), dim3(BS), 0, s, codes, xyz, n, R.P);
+  } else {
+    const unsigned grid = grid_for(n, (size_t)BS, 1u << 30);
+    hipLaunchKernelGGL((k_decode1<L, MODE, BS>), dim3(grid), dim3(BS), 0, s, codes, xyz, n, R.P);
+  }
+  return launch_status();
+}
+
+int reduce_parts(size_t n)
+{
+  size_t g = (n + 256 * 16 - 1) / (256 * 16);
+  if (g < 1) g = 1;
+  if (g > 2048) g = 2048;
+  return (int)g;
+}
+
+template <class L, int MODE>
+static vc_status dot_t(const Resolved& R, const uint64_t* a, const uint64_t* b, size_t n, float* parts, int np,
+                       float* out, hipStream_t s)
+{
+  hipLaunchKernelGGL((k_dot<L, MODE, 256>), dim3(np), dim3(256), 0, s, a, b, n, R.P, parts);
+  vc_status st = launch_status();
+  if (st != VC_SUCCESS) return st;
+  hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(256), 0, s, (const float*)parts, np, out);
+  return launch_status();
+}
+
+template <class L>
+static vc_status norm2_t(const uint64_t* a, size_t n, float* parts, int np, float* out, hipStream_t s)
+{
+  hipLaunchKernelGGL((k_norm2<L, 256>), dim3(np), dim3(256), 0, s, a, n, parts);
+  vc_status st = launch_status();
+  if (st != VC_SUCCESS) return st;
+  hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(256), 0, s, (const float*)parts, np, out);
+  return launch_status();
+}
+
+// layout x mode dispatch
+#define VC_DISPATCH(R, FN, ...)                                                           \
+  do {                                                                                    \
+    switch ((R).layout * 4 + (R).mode) {                                                  \
+      case 0: return FN<L0722, PLAIN>(__VA_ARGS__);                                       \
+      case 1: return FN<L0722, TANH>(__VA_ARGS__);                                        \
+      case 2: return FN<L0722, COS>(__VA_ARGS__);                                         \
+      case 3: return FN<L0722, FRAC>(__VA_ARGS__);                                        \
+      case 4: return FN<L0723, PLAIN>(__VA_ARGS__);                                       \
+      case 8: return FN<L0823, PLAIN>(__VA_ARGS__);                                       \
+      case 12: return FN<L1823, PLAIN>(__VA_ARGS__);                                      \
+      default: return VC_ERROR_UNSUPPORTED_CODEC;                                         \
+    }                                                                                     \
+  } while (0)
+
+vc_status launch_axpy(const Resolved& R, float alpha, const uint64_t* a, const uint64_t* b, uint64_t* c,
+                      size_t n, float* dump, hipStream_t s)
+{
+  VC_DISPATCH(R, axpy_t, R, alpha, a, b, c, n, dump, s);
+}
+
+vc_status launch_encode(const Resolved& R, const float* xyz, uint64_t* codes, size_t n, hipStream_t s)
+{
+  VC_DISPATCH(R, encode_t, R, xyz, codes, n, s);
+}
+
+vc_status launch_decode(const Resolved& R, const uint64_t* codes, float* xyz, size_t n, hipStream_t s)
+{
+  VC_DISPATCH(R, decode_t, R, codes, xyz, n, s);
+}
+
+vc_status launch_dot(const Resolved& R, const uint64_t* a, const uint64_t* b, size_t n, float* parts, int np,
+                     float* out, hipStream_t s)
+{
+  VC_DISPATCH(R, dot_t, R, a, b, n, parts, np, out, s);
+}
+
+vc_status launch_norm2(const Resolved& R, const uint64_t* a, size_t n, float* parts, int np, float* out,
+                       hipStream_t s)
+{
+  switch (R.layout) {
+    case 0: return norm2_t<L0722>(a, n, parts, np, out, s);
+    case 1: return norm2_t<L0723>(a, n, parts, np, out, s);
+    case 2: return norm2_t<L0823>(a, n, parts, np, out, s);
+    case 3: return norm2_t<L1823>(a, n, parts, np, out, s);
+    default: return VC_ERROR_UNSUPPORTED_CODEC;
+  }
+}
+
+}  // namespace vc

@@ -1,0 +1,63 @@
+// CPU emulation build of the device codec (test infrastructure).
+//
+// Compiles paper_2003_02633_amd/csrc/vc_device.hpp for the host with libm
+// stand-ins for the AMDGPU builtins (v_sin/v_cos/v_rsq/v_rcp are replaced by
+// FP64-based equivalents), so the codec's integer logic, octant reduction,
+// double-float level arithmetic and exact magnitude path can be checked against
+// the oracle on a CPU.  Results differ from the GPU only through those
+// transcendental approximations.
+#define VC_HOST_EMULATION 1
+#include "../../paper_2003_02633_amd/csrc/vc_params.hpp"
+
+using namespace vc;
+
+template <class L, int MODE>
+static void enc(const Params& P, const float* xyz, uint64_t* out, size_t n)
+{
+  for (size_t i = 0; i < n; i++) out[i] = encode_vec<L, MODE>(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], P);
+}
+template <class L, int MODE>
+static void dec(const Params& P, const uint64_t* w, float* out, size_t n)
+{
+  for (size_t i = 0; i < n; i++) decode_vec<L, MODE>(w[i], P, out[3 * i], out[3 * i + 1], out[3 * i + 2]);
+}
+
+#define EMU_DISPATCH(R, FN, ...)                      \
+  switch ((R).layout * 4 + (R).mode) {                \
+    case 0: FN<L0722, PLAIN>(__VA_ARGS__); break;     \
+    case 1: FN<L0722, TANH>(__VA_ARGS__); break;      \
+    case 2: FN<L0722, COS>(__VA_ARGS__); break;       \
+    case 3: FN<L0722, FRAC>(__VA_ARGS__); break;      \
+    case 4: FN<L0723, PLAIN>(__VA_ARGS__); break;     \
+    case 8: FN<L0823, PLAIN>(__VA_ARGS__); break;     \
+    case 12: FN<L1823, PLAIN>(__VA_ARGS__); break;    \
+    default: return VC_ERROR_UNSUPPORTED_CODEC;       \
+  }
+
+extern "C" {
+
+int emu_encode(const vc_codec* c, const float* xyz, uint64_t* out, size_t n)
+{
+  Resolved R;
+  vc_status st = resolve(c, &R);
+  if (st != VC_SUCCESS) return st;
+  EMU_DISPATCH(R, enc, R.P, xyz, out, n);
+  return 0;
+}
+
+int emu_decode(const vc_codec* c, const uint64_t* w, float* out, size_t n)
+{
+  Resolved R;
+  vc_status st = resolve(c, &R);
+  if (st != VC_SUCCESS) return st;
+  EMU_DISPATCH(R, dec, R.P, w, out, n);
+  return 0;
+}
+
+int emu_exact_norm(float x, float y, float z, int prec, int keep_sub, uint32_t* j, int* g)
+{
+  exact_norm_round(x, y, z, prec, keep_sub != 0, *j, *g);
+  return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,97 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the public headers
+declare, and rejects invalid arguments synchronously (before any device work)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import paper_2003_02633_amd as vc
+from tests.conftest import ROOT
+
+
+def _declared_symbols():
+    names = set()
+    for h in ("vc.h", "vc_ext.h"):
+        txt = open(os.path.join(ROOT, "include", h)).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        for m in re.finditer(r"\b(vc[bx]?_[a-z0-9_]+)\s*\(", txt):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(vc.LIB_PATH):
+        pytest.fail("libvc.so is not built (run python -m paper_2003_02633_amd.build)")
+    return vc.lib()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared_symbols()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), f"missing export {n}"
+
+
+def test_binding_covers_declared_symbols():
+    declared = set(_declared_symbols())
+    assert declared <= set(vc._SIGS), declared - set(vc._SIGS)
+
+
+def test_status_strings_and_version(lib):
+    assert lib.vc_status_string(0) == b"VC_SUCCESS"
+    assert lib.vc_status_string(7) == b"VC_ERROR_OVERLAP"
+    assert lib.vc_version().startswith(b"libvc")
+
+
+def test_codec_init_layouts(lib):
+    for name, idx in vc.LAYOUTS.items():
+        c = vc.codec(name)
+        assert c.layout == idx and c.struct_size == C.sizeof(vc.vc_codec)
+    c = vc.vc_codec()
+    assert lib.vc_codec_init(C.byref(c), b"0,9,22-16-17") == 3
+
+
+def _fake(addr):
+    return C.c_void_p(addr)
+
+
+def test_validation_errors_without_device_work(lib):
+    c = vc.codec()
+    P = C.byref(c)
+    n = 16
+    # NULL data with n > 0
+    assert lib.vc_encode(P, None, _fake(0x10000), n, None) == 1
+    assert lib.vc_axpy(P, 1.0, None, _fake(0x10000), _fake(0x20000), n, None) == 1
+    # misaligned codes
+    assert lib.vc_decode(P, _fake(0x10004), _fake(0x20000), n, None) == 2
+    assert lib.vc_axpy(P, 1.0, _fake(0x10001), _fake(0x20000), _fake(0x30000), n, None) == 2
+    # partial overlap of output and input (exact aliasing is allowed)
+    assert lib.vc_axpy(P, 1.0, _fake(0x10000), _fake(0x20000), _fake(0x10008), n, None) == 7
+    assert lib.vc_encode(P, _fake(0x10000), _fake(0x10010), n, None) == 7
+    # n == 0 is a no-op even with NULL pointers
+    assert lib.vc_encode(P, None, None, 0, None) == 0
+    assert lib.vc_axpy(P, 1.0, None, None, None, 0, None) == 0
+    # bad codec
+    bad = vc.codec()
+    bad.struct_size = 3
+    assert lib.vc_encode(C.byref(bad), _fake(0x10000), _fake(0x20000), n, None) == 1
+    bad = vc.codec(mode="frac", P=1)
+    assert lib.vc_encode(C.byref(bad), _fake(0x10000), _fake(0x20000), n, None) == 1
+    bad = vc.codec(mode="tanh", gamma=5.0)
+    assert lib.vc_encode(C.byref(bad), _fake(0x10000), _fake(0x20000), n, None) == 3
+    bad = vc.codec("0,8,23-16-17", mode="tanh")
+    assert lib.vc_encode(C.byref(bad), _fake(0x10000), _fake(0x20000), n, None) == 3
+    # reductions need an output
+    assert lib.vc_dot(P, _fake(0x10000), _fake(0x20000), n, None, None) == 1
+    # baselines
+    assert lib.vcb_copy(_fake(0x10000), _fake(0x20008), 64, None) == 2
+    assert lib.vcb_axpy_f32(1.0, None, None, None, 0, None) == 0
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(vc, "_lib", None)
+    monkeypatch.setattr(vc, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError, match="not built"):
+        vc.lib()

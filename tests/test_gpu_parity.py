@@ -1,0 +1,256 @@
+"""GPU parity: the HIP kernels (through the C ABI) against the CPU oracle.
+
+Contract:
+  * encode: codes equal the oracle's bit for bit, except an angle level may differ by one
+    where the exact level coordinate is within one single-precision ulp of the angle of the
+    boundary (counted); magnitude fields exact.
+  * decode: |x_gpu - x_oracle| <= 1e-6 r_hat per component; zero/reserved codes exact/NaN.
+  * axpy (layered): the fused kernel's codes equal the GPU encode of its own pre-encode
+    single-precision sum (dumped by the verification variant of the same kernel); those codes
+    follow the encode rule against the oracle; decoding them recovers the FP64 sum of the
+    exactly decoded operands within the codec error bound.
+  * dot / norm2: within 4e-6 of sum |a||b| (resp. sum |a|^2) of the FP64 oracle.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2003_02633_amd as vc
+from paper_2003_02633_amd import inputs
+from tests.parity import classify, decode_err, describe_bad
+
+pytestmark = pytest.mark.gpu
+
+ALPHA = float(np.float32(0.7))
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU test without a GPU"
+    vc.lib()
+    return torch
+
+
+def up(torch, arr):
+    arr = np.ascontiguousarray(arr)
+    if arr.dtype == np.uint64:
+        arr = arr.view(np.int64)
+    return torch.from_numpy(arr).to("cuda")
+
+
+def down(t, u64=False):
+    a = t.cpu().numpy()
+    return a.view(np.uint64) if u64 else a
+
+
+def gpu_encode(torch, c, xyz):
+    out = vc.vc_encode(c, up(torch, xyz.astype(np.float32)))
+    torch.cuda.synchronize()
+    return down(out, True)
+
+
+def _summary(res):
+    return {k: v for k, v in res.items() if not isinstance(v, np.ndarray)}
+
+
+# ----------------------------------------------------------------------------- encode
+def test_encode_config1(torch_dev):
+    """N = 65,536 N(0,1) vectors plus the axis/zero/extreme edge cases."""
+    say("case: encode config1 N=65547")
+    c, co = vc.codec(), O.codec()
+    xyz = inputs.gaussian_with_edges(65536, 0)
+    dev = gpu_encode(torch_dev, c, xyz)
+    res = classify(co, xyz, dev)
+    say(f"encode config1: {_summary(res)}")
+    assert res["other"] == 0, describe_bad(co, xyz, dev, res)
+    # the 11 edge cases are exact (axis ties, zero, flush, saturation)
+    assert np.array_equal(dev[-11:], res["ref"][-11:])
+
+
+VARIANTS = [
+    ("0,7,22-17-18", "plain", {}),
+    ("0,7,23-17-17", "plain", {}),
+    ("0,8,23-16-17", "plain", {}),
+    ("1,8,23-16-16", "plain", {}),
+    ("0,7,22-17-18", "frac", {"P": 1 << 16}),
+    ("0,7,22-17-18", "frac", {"P": 1 << 17}),
+    ("0,7,22-17-18", "frac", {"P": 163840}),
+    ("0,7,22-17-18", "frac", {"P": 1 << 18}),
+]
+
+
+@pytest.mark.parametrize("layout,mode,kw", VARIANTS)
+def test_encode_decode_variants(torch_dev, layout, mode, kw):
+    say(f"case: variant {layout} {mode} {kw}")
+    c, co = vc.codec(layout, mode=mode, **kw), O.codec(layout, mode=mode, **kw)
+    for name, xyz in [("sphere_log", inputs.sphere_loguniform(1 << 18, 1)),
+                      ("vmf_pole", inputs.vmf(1 << 16, 1000.0, seed=5)),
+                      ("gauss", inputs.gaussian_with_edges(1 << 16, 3))]:
+        dev = gpu_encode(torch_dev, c, xyz)
+        res = classify(co, xyz, dev)
+        say(f"  {name}: {_summary(res)}")
+        assert res["other"] == 0, describe_bad(co, xyz, dev, res)
+        w = O.encode(co, xyz)
+        d = vc.vc_decode(c, up(torch_dev, w))
+        torch_dev.cuda.synchronize()
+        err, nan_ok = decode_err(co, w, down(d))
+        say(f"  {name}: decode max err/r = {err:.3e}")
+        assert nan_ok and err <= 1e-6
+
+
+def test_decode_random_codes(torch_dev):
+    """Every valid code (random fields) plus zero and reserved codes."""
+    say("case: decode random codes")
+    c, co = vc.codec(), O.codec()
+    g = np.random.default_rng(7)
+    n = 1 << 18
+    E = g.integers(1, 127, n, dtype=np.uint64)
+    M = g.integers(0, 1 << 22, n, dtype=np.uint64)
+    P = g.integers(0, 1 << 17, n, dtype=np.uint64)
+    T = g.integers(0, 1 << 18, n, dtype=np.uint64)
+    w = (E << np.uint64(57)) | (M << np.uint64(35)) | (P << np.uint64(18)) | T
+    w[:4] = [0, 127 << 57, (127 << 57) | 12345, 1 << 57]
+    d = down(vc.vc_decode(c, up(torch_dev, w)))
+    err, nan_ok = decode_err(co, w, d)
+    say(f"decode random codes: max err/r = {err:.3e}")
+    assert nan_ok and err <= 1e-6
+    assert (d[0] == 0).all() and np.isnan(d[1]).all() and np.isnan(d[2]).all()
+
+
+# ----------------------------------------------------------------------------- axpy
+def _axpy_operands(n, seed_a, seed_b):
+    xa = inputs.gaussian_with_edges(n, seed_a)
+    xb = inputs.gaussian_with_edges(n, seed_b)
+    xb[-11:-4] = -xa[-11:-4]          # negated axes/zero: a + b hits exact zero
+    return xa, xb
+
+
+def _check_axpy(torch, c, co, wa, wb, alpha, label):
+    ta, tb = up(torch, wa), up(torch, wb)
+    out = vc.vc_axpy(c, alpha, ta, tb)
+    out2, c32 = vc.vcx_axpy_dump(c, alpha, ta, tb)
+    torch.cuda.synchronize()
+    wc, wc2, c32 = down(out, True), down(out2, True), down(c32)
+    # 1. fused kernel == verification variant == GPU encode of the pre-encode sum
+    assert np.array_equal(wc, wc2)
+    assert np.array_equal(wc, gpu_encode(torch, c, c32))
+    # 2. encode rule against the oracle on the same single-precision sums
+    res = classify(co, c32, wc)
+    say(f"{label}: encode-of-sum {_summary(res)}")
+    assert res["other"] == 0, describe_bad(co, c32, wc, res)
+    # 3. end to end vs the FP64 sum of the exactly decoded operands
+    A64, B64 = O.decode64(co, wa), O.decode64(co, wb)
+    c64 = alpha * A64 + B64
+    got = O.decode64(co, wc)
+    nrm = np.linalg.norm(c64, axis=1)
+    scale = alpha * np.linalg.norm(A64, axis=1) + np.linalg.norm(B64, axis=1)
+    ok = (nrm > 2.0 ** -70) & (nrm < 1e14)
+    nt, npm = O.nmax(co)
+    codec_bound = math.hypot(math.pi / nt, math.pi / (2 * npm)) + 2.0 ** -23
+    err = np.linalg.norm(got - c64, axis=1)[ok]
+    allowed = codec_bound * nrm[ok] + (4 * 2.0 ** -24 + 1e-6) * scale[ok]
+    say(f"{label}: max end-to-end err/allowed = {(err / allowed).max():.3f}")
+    assert (err <= allowed).all()
+    # exact zeros: a + b == 0 exactly where b = -a
+    z = np.all(c64 == 0, axis=1)
+    assert (wc[z] == 0).all()
+    # 4. field-wise agreement with the oracle's own axpy (reported)
+    ref = O.axpy(co, alpha, wa, wb)
+    same = np.mean(ref == wc)
+    say(f"{label}: identical to oracle axpy codes: {same * 100:.4f} %")
+    return wc
+
+
+def test_axpy_config1(torch_dev):
+    """c = a + b (alpha = 1) and alpha = 0.7 on the N(0,1) + edge-case operands."""
+    say("case: axpy config1")
+    c, co = vc.codec(), O.codec()
+    xa, xb = _axpy_operands(65536, 0, 1)
+    wa, wb = O.encode(co, xa), O.encode(co, xb)
+    _check_axpy(torch_dev, c, co, wa, wb, 1.0, "axpy config1 alpha=1")
+    _check_axpy(torch_dev, c, co, wa, wb, ALPHA, "axpy config1 alpha=0.7")
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 511, 512, 513, 1023, 1025, 4099])
+def test_axpy_ragged_and_unaligned(torch_dev, n):
+    say(f"case: axpy ragged n={n}")
+    torch = torch_dev
+    c, co = vc.codec(), O.codec()
+    xa, xb = inputs.sphere_loguniform(n + 1, 11), inputs.sphere_loguniform(n + 1, 12)
+    wa, wb = O.encode(co, xa), O.encode(co, xb)
+    ref_gpu = _check_axpy(torch, c, co, wa[:n], wb[:n], ALPHA, f"axpy n={n}")
+    # element offset 1: 8-byte aligned but not 16-byte aligned -> scalar path
+    ta, tb = up(torch, wa), up(torch, wb)
+    out = torch.zeros(n + 1, dtype=torch.int64, device="cuda")
+    vc.vc_axpy(c, ALPHA, ta[1:], tb[1:], out[1:])
+    torch.cuda.synchronize()
+    got = down(out, True)
+    assert got[0] == 0
+    ref_shift = _check_axpy(torch, c, co, wa[1:], wb[1:], ALPHA, f"axpy n={n} offset")
+    assert np.array_equal(got[1:], ref_shift)
+    # in-place (c aliases a)
+    vc.vc_axpy(c, ALPHA, ta[:n], tb[:n], ta[:n])
+    torch.cuda.synchronize()
+    assert np.array_equal(down(ta, True)[:n], ref_gpu)
+
+
+def test_encode_decode_ragged_unaligned(torch_dev):
+    torch = torch_dev
+    c, co = vc.codec(), O.codec()
+    for n in (1, 3, 4, 5, 1021, 4096 + 7):
+        say(f"case: encode/decode ragged n={n}")
+        xyz = inputs.sphere_loguniform(n + 1, 13)
+        t = up(torch, xyz)
+        codes = torch.zeros(n + 1, dtype=torch.int64, device="cuda")
+        vc.vc_encode(c, t[1:], codes[1:])                  # 12-byte offset: scalar path
+        codes_a = vc.vc_encode(c, t[:n].contiguous())      # aligned path
+        torch.cuda.synchronize()
+        res = classify(co, xyz[1:], down(codes, True)[1:])
+        assert res["other"] == 0
+        res = classify(co, xyz[:n], down(codes_a, True))
+        assert res["other"] == 0
+        w = O.encode(co, xyz)
+        tw = up(torch, w)
+        out = torch.zeros((n + 1) * 3, dtype=torch.float32, device="cuda")
+        vc.vc_decode(c, tw[1:], out[3:].view(n, 3))
+        torch.cuda.synchronize()
+        err, nan_ok = decode_err(co, w[1:], down(out)[3:].reshape(n, 3))
+        assert nan_ok and err <= 1e-6 and (down(out)[:3] == 0).all()
+
+
+def test_zero_length_and_empty(torch_dev):
+    torch = torch_dev
+    c = vc.codec()
+    e = torch.empty(0, dtype=torch.int64, device="cuda")
+    assert vc.vc_axpy(c, 1.0, e, e).numel() == 0
+    out = vc.vc_norm2(c, e)
+    torch.cuda.synchronize()
+    assert float(out.cpu()[0]) == 0.0
+
+
+# ----------------------------------------------------------------------------- reductions
+@pytest.mark.parametrize("n", [1, 1000, 65547, 1 << 20])
+def test_dot_norm2(torch_dev, n):
+    say(f"case: dot/norm2 n={n}")
+    torch = torch_dev
+    c, co = vc.codec(), O.codec()
+    wa = O.encode(co, inputs.gaussian_with_edges(n, 21)[:n])
+    wb = O.encode(co, inputs.gaussian_with_edges(n, 22)[:n])
+    ta, tb = up(torch, wa), up(torch, wb)
+    d = float(vc.vc_dot(c, ta, tb).cpu()[0])
+    s = float(vc.vc_norm2(c, ta).cpu()[0])
+    ref_d, ref_s = O.dot(co, wa, wb), O.norm2(co, wa)
+    A, B = O.decode64(co, wa), O.decode64(co, wb)
+    scale = float((np.linalg.norm(A, axis=1) * np.linalg.norm(B, axis=1)).sum())
+    say(f"dot n={n}: gpu {d:.9e} oracle {ref_d:.9e}; norm2 gpu {s:.9e} oracle {ref_s:.9e}")
+    assert abs(d - ref_d) <= 4e-6 * scale
+    assert abs(s - ref_s) <= 4e-6 * ref_s
