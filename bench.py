@@ -1,0 +1,297 @@
+#!/usr/bin/env python3
+"""Benchmark of the compressed 3-vector axpy on one MI355X.
+
+Workload (one "step" = one pass of the whole hot path = one launch of the fused
+decode-FMA-encode kernel): c = alpha*a + b on N = 2^27 compressed 3-vectors
+(<0,7,22>-17-18 codes, 1 GiB per operand), directions uniform on S^2, magnitudes
+log-uniform on [1e-6, 1e6], alpha = 0.7.  Inputs are generated and encoded on the
+GPU before timing, so they are resident in HBM.
+
+Prints one JSON line: metric/value (Gvec/s of the compressed axpy), the HBM
+roofline of that kernel, the CPU oracle timed on the host on a bounded sample, and
+side-by-side figures: uncompressed FP32 / BF16 / FP16 axpy on the same GPU, a copy
+kernel (attainable bandwidth), encode/decode/dot/norm2, and the codec variants.
+
+Usage: python bench.py [--steps K] [--warmup W] [--n N] [--quick] [--no-cpu]
+       python bench.py --pmc-run     (launch copy + axpy once each, for rocprofv3 --pmc)
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E spec
+ALPHA = 0.699999988079071      # float32(0.7)
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "axpy_n2p27_traffic.txt")
+KERNEL_SOURCES = ["paper_2003_02633_amd/csrc/vc_device.hpp", "paper_2003_02633_amd/csrc/vc_stream.hip",
+                  "paper_2003_02633_amd/csrc/vc_coeffs.inc"]
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(n: int):
+    """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it was taken on the
+    current kernel sources and this N; otherwise None."""
+    if not os.path.exists(PROFILE_TRAFFIC):
+        return None
+    kv = {}
+    with open(PROFILE_TRAFFIC) as f:
+        for line in f:
+            if "=" in line and not line.startswith("#"):
+                k, v = line.split("=", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_hash") != kernel_hash() or int(kv.get("n_vectors", -1)) != n:
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def timed(torch, fn, steps: int, warmup: int) -> float:
+    """Average milliseconds per call of fn() (all work on torch's current stream)."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(steps):
+        fn()
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def cpu_baseline(torch, wa_dev, wb_dev, target_s: float = 10.0):
+    """Time the oracle's compressed axpy on the host, all cores, on a bounded prefix sample."""
+    import numpy as np
+
+    import oracle as O
+
+    co = O.codec()
+    threads = O.max_threads()
+    n_cal = 1 << 16
+    wa = wa_dev[:n_cal].cpu().numpy().view(np.uint64)
+    wb = wb_dev[:n_cal].cpu().numpy().view(np.uint64)
+    t = time.perf_counter()
+    O.axpy(co, ALPHA, wa, wb, threads)
+    rate = n_cal / max(time.perf_counter() - t, 1e-6)
+    n = int(min(wa_dev.numel(), max(n_cal, min(1 << 25, rate * target_s))))
+    wa = wa_dev[:n].cpu().numpy().view(np.uint64)
+    wb = wb_dev[:n].cpu().numpy().view(np.uint64)
+    t = time.perf_counter()
+    O.axpy(co, ALPHA, wa, wb, threads)
+    dt = time.perf_counter() - t
+    return {"value": n / dt / 1e9, "unit": "Gvec/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {n} vectors of the benchmark operands; oracle compressed axpy "
+                      f"(decode both, single-rounded FMA, encode), OpenMP over {threads} threads, {dt:.1f} s"}
+
+
+def sample_error(torch, wa, wb, wc, nsample: int = 1 << 20, seed: int = 5):
+    """Max normalised error |decode(c) - (alpha a_hat + b_hat)| / |alpha a_hat + b_hat| over a seeded
+    sample (FP64 from the exactly decoded operands, by the oracle)."""
+    import numpy as np
+
+    import oracle as O
+
+    co = O.codec()
+    n = wa.numel()
+    g = torch.Generator(device="cpu")
+    g.manual_seed(seed)
+    idx = torch.randint(0, n, (min(nsample, n),), generator=g).to(wa.device)
+    a = wa[idx].cpu().numpy().view(np.uint64)
+    b = wb[idx].cpu().numpy().view(np.uint64)
+    c = wc[idx].cpu().numpy().view(np.uint64)
+    c64 = ALPHA * O.decode64(co, a) + O.decode64(co, b)
+    got = O.decode64(co, c)
+    nrm = np.linalg.norm(c64, axis=1)
+    scale = ALPHA * np.linalg.norm(O.decode64(co, a), axis=1) + np.linalg.norm(O.decode64(co, b), axis=1)
+    ok = nrm > 0
+    err = np.linalg.norm(got - c64, axis=1)
+    return {"max_rel_err": float((err[ok] / nrm[ok]).max()),
+            "mean_rel_err": float((err[ok] / nrm[ok]).mean()),
+            "max_err_over_operand_scale": float((err[ok] / scale[ok]).max()),
+            "sample": int(idx.numel())}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=1 << 27)
+    ap.add_argument("--quick", action="store_true", help="skip the side-by-side extras")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--pmc-run", action="store_true", help="one copy + one axpy launch (profiling)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (--gpus {args.gpus} requested); "
+              "the method is data-parallel over independent vectors and its multi-GPU sharding is "
+              "described in DESIGN.md, but no multi-GPU path is built.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2003_02633_amd as vc
+    from paper_2003_02633_amd import inputs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    vc.lib()
+    N = args.n
+    dev = torch.device("cuda:0")
+    c = vc.codec()
+    log(f"generating inputs N={N}")
+    a32 = inputs.sphere_loguniform_torch(N, 0, dev)
+    b32 = inputs.sphere_loguniform_torch(N, 1, dev)
+    wa = vc.vc_encode(c, a32)
+    wb = vc.vc_encode(c, b32)
+    wc = torch.empty_like(wa)
+    torch.cuda.synchronize()
+
+    if args.pmc_run:
+        cp_src = torch.empty(N * 3, dtype=torch.float32, device=dev)
+        cp_src.copy_(a32.view(-1))
+        cp_dst = torch.empty_like(cp_src)
+        vc.vcb_copy(cp_src, cp_dst)
+        torch.cuda.synchronize()
+        vc.vc_axpy(c, ALPHA, wa, wb, wc)
+        torch.cuda.synchronize()
+        print(json.dumps({"pmc_run": True, "n_vectors": N, "copy_bytes_each_way": N * 12,
+                          "kernel_hash": kernel_hash()}), flush=True)
+        return
+
+    log(f"timing compressed axpy: warmup {args.warmup}, steps {args.steps}")
+    ms = timed(torch, lambda: vc.vc_axpy(c, ALPHA, wa, wb, wc), args.steps, args.warmup)
+    gvecs = N / (ms * 1e-3) / 1e9
+    achieved = 24.0 * N / (ms * 1e-3) / 1e9
+    log(f"compressed axpy: {ms:.3f} ms/step, {gvecs:.2f} Gvec/s, {achieved:.0f} GB/s")
+
+    err = sample_error(torch, wa, wb, wc)
+    log(f"sample error: {err}")
+
+    extras = {}
+    if not args.quick:
+        k = max(3, args.steps // 4)
+        # uncompressed FP32 axpy over the same vectors (36 B/vec)
+        c32 = torch.empty_like(a32)
+        ms_f32 = timed(torch, lambda: vc.vcb_axpy_f32(ALPHA, a32, b32, c32), k, 2)
+        extras["fp32_axpy"] = {"gvecs": N / (ms_f32 * 1e-3) / 1e9, "ms": ms_f32,
+                               "GBs": 36.0 * N / (ms_f32 * 1e-3) / 1e9}
+        extras["speedup_vs_fp32"] = ms_f32 / ms
+        log(f"fp32 axpy: {ms_f32:.3f} ms -> speedup {ms_f32 / ms:.3f}")
+        del c32
+        # bf16 / fp16 storage padded to 4 x 16 bit (8 B/vec, the bytes of a code)
+        for kind, dt in (("bf16", torch.bfloat16), ("f16", torch.float16)):
+            ha = torch.zeros((N, 4), dtype=dt, device=dev)
+            hb = torch.zeros((N, 4), dtype=dt, device=dev)
+            ha[:, :3] = a32
+            hb[:, :3] = b32
+            hc = torch.empty_like(ha)
+            iv = (ha.view(torch.int16), hb.view(torch.int16), hc.view(torch.int16))
+            ms_h = timed(torch, lambda: vc.vcb_axpy_h4(kind, ALPHA, *iv), k, 2)
+            rec = {"gvecs": N / (ms_h * 1e-3) / 1e9, "ms": ms_h, "GBs": 24.0 * N / (ms_h * 1e-3) / 1e9}
+            if kind == "f16":
+                big = (a32.abs() > 65504).any(dim=1).sum().item()
+                small = ((a32.abs() < 6.1e-5) & (a32 != 0)).any(dim=1).sum().item()
+                rec["overflow_fraction"] = big / N
+                rec["subnormal_fraction"] = small / N
+            extras[f"{kind}x4_axpy"] = rec
+            log(f"{kind}x4 axpy: {ms_h:.3f} ms")
+            del ha, hb, hc, iv
+        # attainable bandwidth: copy of 2 x 12 N bytes
+        src = a32.view(-1)
+        dst = torch.empty_like(src)
+        ms_cp = timed(torch, lambda: vc.vcb_copy(src, dst), k, 2)
+        copy_gbs = 2.0 * 12 * N / (ms_cp * 1e-3) / 1e9
+        extras["copy"] = {"GBs": copy_gbs, "ms": ms_cp, "bytes": 24 * N}
+        extras["axpy_frac_of_copy_bw"] = achieved / copy_gbs
+        del dst
+        # encode / decode / reductions of the same data
+        ms_enc = timed(torch, lambda: vc.vc_encode(c, a32, wc), k, 2)
+        xyz = torch.empty_like(a32)
+        ms_dec = timed(torch, lambda: vc.vc_decode(c, wa, xyz), k, 2)
+        del xyz
+        out1 = torch.empty(1, dtype=torch.float32, device=dev)
+        ms_dot = timed(torch, lambda: vc.vc_dot(c, wa, wb, out1), k, 2)
+        ms_n2 = timed(torch, lambda: vc.vc_norm2(c, wa, out1), k, 2)
+        extras["encode"] = {"gvecs": N / (ms_enc * 1e-3) / 1e9, "GBs": 20.0 * N / (ms_enc * 1e-3) / 1e9}
+        extras["decode"] = {"gvecs": N / (ms_dec * 1e-3) / 1e9, "GBs": 20.0 * N / (ms_dec * 1e-3) / 1e9}
+        extras["dot"] = {"gvecs": N / (ms_dot * 1e-3) / 1e9, "GBs": 16.0 * N / (ms_dot * 1e-3) / 1e9}
+        extras["norm2"] = {"gvecs": N / (ms_n2 * 1e-3) / 1e9, "GBs": 8.0 * N / (ms_n2 * 1e-3) / 1e9}
+        log(f"encode {ms_enc:.3f} ms, decode {ms_dec:.3f} ms, dot {ms_dot:.3f} ms, norm2 {ms_n2:.3f} ms")
+        # codec variants of the same axpy
+        var = {}
+        for name, kw in (("frac_P2^16", {"mode": "frac", "P": 1 << 16}),
+                         ("frac_P163840", {"mode": "frac", "P": 163840}),
+                         ("frac_P2^18", {"mode": "frac", "P": 1 << 18}),
+                         ("tanh_g0.5", {"mode": "tanh", "gamma": 0.5}),
+                         ("cos", {"mode": "cos"})):
+            cv = vc.codec(**kw)
+            va_ = vc.vc_encode(cv, a32)
+            vb_ = vc.vc_encode(cv, b32)
+            msv = timed(torch, lambda: vc.vc_axpy(cv, ALPHA, va_, vb_, wc), k, 2)
+            var[name] = {"gvecs": N / (msv * 1e-3) / 1e9, "GBs": 24.0 * N / (msv * 1e-3) / 1e9}
+            log(f"variant {name}: {msv:.3f} ms")
+            del va_, vb_
+        extras["variants_axpy"] = var
+        extras["paper_titanv_speedup_context"] = 1.5
+        torch.cuda.synchronize()
+        # restore the plain result for consistency
+        vc.vc_axpy(c, ALPHA, wa, wb, wc)
+
+    cpu = None
+    if not args.no_cpu:
+        log("timing the CPU oracle on a bounded sample")
+        cpu = cpu_baseline(torch, wa, wb)
+        log(f"cpu oracle: {cpu}")
+
+    rec = {
+        "metric": "compressed vs FP32 axpy: Gvec/s, effective HBM GB/s (% peak), max rel err",
+        "value": gvecs,
+        "unit": "Gvec/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "compressed axpy c = 0.7 a + b, N = 2^27 3-vectors, <0,7,22>-17-18 codes, "
+                               "directions uniform on S^2, |x| log-uniform [1e-6, 1e6]",
+                   "n_vectors": N, "codec": "0,7,22-17-18 plain RNE", "alpha": ALPHA},
+        "effective_GBs": achieved,
+        "pct_hbm_peak": 100.0 * achieved / HBM_PEAK_GBS,
+        "error": err,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": read_traffic(N),
+                     "algorithmic_bytes_per_launch": 24 * N},
+        "cpu_baseline": cpu,
+        "extras": extras,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -184,3 +184,23 @@ def segments(nseg: int = 64, seed: int = 3, lo_exp: float = 3.0, hi_exp: float =
     tags = np.array([ops[i % len(ops)] for i in range(nseg)])
     g.shuffle(tags)
     return lengths, list(tags)
+
+
+def sphere_loguniform_torch(n: int, seed: int, device="cuda", lo_exp: float = -6.0, hi_exp: float = 6.0,
+                            chunk: int = 1 << 24):
+    """GPU-side draw of the ``sphere_loguniform`` distribution (torch's seeded Philox generator):
+    directions = normalised FP64 Gaussians, |x| = 10^U[lo_exp, hi_exp], rounded to FP32.
+    Used for the large benchmark inputs, which are generated where they are consumed."""
+    import torch
+
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    out = torch.empty((n, 3), dtype=torch.float32, device=device)
+    for s in range(0, n, chunk):
+        e = min(n, s + chunk)
+        d = torch.randn((e - s, 3), generator=g, dtype=torch.float64, device=device)
+        d = d / torch.linalg.vector_norm(d, dim=1, keepdim=True).clamp_min(1e-300)
+        r = torch.pow(10.0, torch.empty((e - s, 1), dtype=torch.float64, device=device).uniform_(
+            lo_exp, hi_exp, generator=g))
+        out[s:e] = (d * r).to(torch.float32)
+    return out
