@@ -142,6 +142,8 @@ def main():
     ap.add_argument("--quick", action="store_true", help="skip the side-by-side extras")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--pmc-run", action="store_true", help="one copy + one axpy launch (profiling)")
+    ap.add_argument("--precision", default="f64", choices=["f64", "f32"],
+                    help="encoder arithmetic of the headline codec")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -159,7 +161,7 @@ def main():
     vc.lib()
     N = args.n
     dev = torch.device("cuda:0")
-    c = vc.codec()
+    c = vc.codec(precision=args.precision)
     log(f"generating inputs N={N}")
     a32 = inputs.sphere_loguniform_torch(N, 0, dev)
     b32 = inputs.sphere_loguniform_torch(N, 1, dev)
@@ -239,6 +241,14 @@ def main():
         extras["dot"] = {"gvecs": N / (ms_dot * 1e-3) / 1e9, "GBs": 16.0 * N / (ms_dot * 1e-3) / 1e9}
         extras["norm2"] = {"gvecs": N / (ms_n2 * 1e-3) / 1e9, "GBs": 8.0 * N / (ms_n2 * 1e-3) / 1e9}
         log(f"encode {ms_enc:.3f} ms, decode {ms_dec:.3f} ms, dot {ms_dot:.3f} ms, norm2 {ms_n2:.3f} ms")
+        # the other encoder precision on the same operands
+        other = "f32" if args.precision == "f64" else "f64"
+        co_ = vc.codec(precision=other)
+        ms_o = timed(torch, lambda: vc.vc_axpy(co_, ALPHA, wa, wb, wc), k, 2)
+        extras[f"axpy_encoder_{other}"] = {"gvecs": N / (ms_o * 1e-3) / 1e9, "ms": ms_o,
+                                           "GBs": 24.0 * N / (ms_o * 1e-3) / 1e9,
+                                           "speedup_vs_fp32": extras["fp32_axpy"]["ms"] / ms_o}
+        log(f"axpy with {other} encoder: {ms_o:.3f} ms")
         # codec variants of the same axpy
         var = {}
         for name, kw in (("frac_P2^16", {"mode": "frac", "P": 1 << 16}),
@@ -246,7 +256,7 @@ def main():
                          ("frac_P2^18", {"mode": "frac", "P": 1 << 18}),
                          ("tanh_g0.5", {"mode": "tanh", "gamma": 0.5}),
                          ("cos", {"mode": "cos"})):
-            cv = vc.codec(**kw)
+            cv = vc.codec(precision=args.precision, **kw)
             va_ = vc.vc_encode(cv, a32)
             vb_ = vc.vc_encode(cv, b32)
             msv = timed(torch, lambda: vc.vc_axpy(cv, ALPHA, va_, vb_, wc), k, 2)
@@ -280,7 +290,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "compressed axpy c = 0.7 a + b, N = 2^27 3-vectors, <0,7,22>-17-18 codes, "
                                "directions uniform on S^2, |x| log-uniform [1e-6, 1e6]",
-                   "n_vectors": N, "codec": "0,7,22-17-18 plain RNE", "alpha": ALPHA},
+                   "n_vectors": N, "codec": "0,7,22-17-18 plain RNE", "alpha": ALPHA,
+                   "encoder_precision": args.precision},
         "effective_GBs": achieved,
         "pct_hbm_peak": 100.0 * achieved / HBM_PEAK_GBS,
         "error": err,

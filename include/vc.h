@@ -67,6 +67,13 @@ typedef enum { VC_MAG_RNE = 0, VC_MAG_TRUNC = 1 } vc_mag_round;
 
 enum { VC_COMPAND_PHI = 1, VC_COMPAND_THETA = 2 };
 
+/* arithmetic of the encoder's norm, angle ratios and level coordinates: double precision
+ * (the paper's implementation section prescribes it for phi; full-rate FMA on MI355X), or
+ * single precision only, with double-float error-free transformations.  Both produce the
+ * same codes up to the one-ulp window; decode and all post-decode arithmetic are single
+ * precision in both. */
+typedef enum { VC_PREC_F64 = 0, VC_PREC_F32 = 1 } vc_precision;
+
 /* Codec description.  Plain data, owned by the caller; build it with vc_codec_init
  * and adjust fields before use.  struct_size versions the layout. */
 typedef struct {
@@ -75,14 +82,16 @@ typedef struct {
   uint32_t mode;          /* vc_mode */
   uint32_t mag_round;     /* vc_mag_round */
   uint32_t compand_mask;  /* VC_COMPAND_* bits: angles a companding map applies to */
-  float gamma;            /* tanh companding parameter (§2.5), > 0 */
+  float gamma;            /* tanh companding parameter (§2.5), in (0, 1] */
   uint64_t frac_P;        /* fractional split: n_phi_max + 1 (§2.4, Eq. q_split) */
+  uint32_t precision;     /* vc_precision of the encoder */
+  uint32_t reserved0;     /* must be 0 */
 } vc_codec;
 
 /* Fill *c with the plain codec of `layout` ("0,7,22-17-18", "0,7,23-17-17",
  * "0,8,23-16-17", "1,8,23-16-16"; NULL selects the default <0,7,22>-17-18),
  * RNE magnitude, companding of both angles with gamma = 0.5 when a companding mode
- * is later selected, frac_P = 2^17.  Host-only, no device work. */
+ * is later selected, frac_P = 2^17, double-precision encoder arithmetic.  Host-only. */
 vc_status vc_codec_init(vc_codec* c, const char* layout);
 
 /* Encode n float32 vectors (device, AoS [n][3]) into n codes (device).  §3: three
@@ -115,7 +124,8 @@ vc_status vc_norm2(const vc_codec* c, const uint64_t* a, size_t n, float* d_out,
  * element e, out[e] (rows x 3, float32) = M (rows x cols, float32 row-major, device)
  * times decode(U[e]) (cols vectors, codes [n_elem][cols], device).  Contraction on
  * the matrix cores in single precision with single-precision accumulation.
- * rows <= 256, cols <= 256. */
+ * 1 <= rows <= 256, 1 <= cols <= 256 and 4 ceil(cols/4) rows <= 20480 (the operator is staged
+ * in LDS), else VC_ERROR_INVALID_VALUE. */
 vc_status vc_fused_apply(const vc_codec* c, const float* M, int rows, int cols, const uint64_t* U,
                          float* out, size_t n_elem, hipStream_t stream);
 

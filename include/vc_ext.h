@@ -38,6 +38,16 @@ vc_status vcb_axpy_bf16x4(float alpha, const uint16_t* a, const uint16_t* b, uin
 vc_status vcb_axpy_f16x4(float alpha, const uint16_t* a, const uint16_t* b, uint16_t* c, size_t nvec,
                          hipStream_t stream);
 
+/* Launch configuration of the streaming compressed axpy (default layout, uniform
+ * quantisation): threads per block (128, 256, 512), vectors per thread and grid step
+ * (2 or 4), non-temporal loads/stores (0/1).  Process-wide; not thread-safe with
+ * concurrent launches.  Unsupported combinations return VC_ERROR_UNSUPPORTED_CODEC.
+ * vcx_load_tuning reads "axpy block=B vpt=V nt=T" lines from a text file (the cache the
+ * autotuner writes); the library applies the file named by $VC_TUNE_CACHE on first use. */
+vc_status vcx_set_stream_config(int block, int vpt, int nt);
+vc_status vcx_get_stream_config(int* block, int* vpt, int* nt);
+vc_status vcx_load_tuning(const char* path);
+
 /* dst[0:bytes) = src[0:bytes): the attainable-bandwidth reference.  16-byte aligned. */
 vc_status vcb_copy(const void* src, void* dst, size_t bytes, hipStream_t stream);
 

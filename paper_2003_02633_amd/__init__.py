@@ -35,7 +35,7 @@ class vc_codec(C.Structure):
     """Mirror of ``vc_codec`` in include/vc.h."""
     _fields_ = [("struct_size", C.c_uint32), ("layout", C.c_uint32), ("mode", C.c_uint32),
                 ("mag_round", C.c_uint32), ("compand_mask", C.c_uint32), ("gamma", C.c_float),
-                ("frac_P", C.c_uint64)]
+                ("frac_P", C.c_uint64), ("precision", C.c_uint32), ("reserved0", C.c_uint32)]
 
 
 class vc_segment(C.Structure):
@@ -66,6 +66,9 @@ _SIGS = {
     "vcb_axpy_bf16x4": ([C.c_float, _vp, _vp, _vp, C.c_size_t, _vp], C.c_int),
     "vcb_axpy_f16x4": ([C.c_float, _vp, _vp, _vp, C.c_size_t, _vp], C.c_int),
     "vcb_copy": ([_vp, _vp, C.c_size_t, _vp], C.c_int),
+    "vcx_set_stream_config": ([C.c_int, C.c_int, C.c_int], C.c_int),
+    "vcx_get_stream_config": ([C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
+    "vcx_load_tuning": ([C.c_char_p], C.c_int),
 }
 
 
@@ -89,10 +92,14 @@ def _check(st: int, where: str):
         raise VcError(st, where)
 
 
+PRECISIONS = {"f64": 0, "f32": 1}
+
+
 def codec(layout: str = "0,7,22-17-18", mode: str = "plain", gamma: float = 0.5, P: int = 1 << 17,
-          compand: str = "both") -> vc_codec:
+          compand: str = "both", precision: str = "f64") -> vc_codec:
     c = vc_codec()
     _check(lib().vc_codec_init(C.byref(c), layout.encode()), "vc_codec_init")
+    c.precision = PRECISIONS[precision]
     c.mode = MODES[mode]
     c.gamma = float(gamma)
     c.frac_P = int(P)
@@ -221,6 +228,16 @@ def vcb_copy(src, dst, stream=None):
     nbytes = src.numel() * src.element_size()
     _check(lib().vcb_copy(_ptr(src), _ptr(dst), nbytes, _stream(stream)), "vcb_copy")
     return dst
+
+
+def set_stream_config(block: int, vpt: int, nt: int):
+    _check(lib().vcx_set_stream_config(block, vpt, nt), "vcx_set_stream_config")
+
+
+def get_stream_config():
+    b, v, t = C.c_int(), C.c_int(), C.c_int()
+    _check(lib().vcx_get_stream_config(C.byref(b), C.byref(v), C.byref(t)), "vcx_get_stream_config")
+    return b.value, v.value, t.value
 
 
 class BatchPlan:

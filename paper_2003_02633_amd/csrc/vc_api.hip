@@ -1,5 +1,7 @@
 // vc_api.hip -- C ABI of libvc: argument validation, codec resolution, dispatch.
 #include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include "vc_internal.hpp"
@@ -40,6 +42,7 @@ vc_status vc_codec_init(vc_codec* c, const char* layout)
   c->compand_mask = VC_COMPAND_PHI | VC_COMPAND_THETA;
   c->gamma = 0.5f;
   c->frac_P = 1ull << 17;
+  c->precision = VC_PREC_F64;
   return VC_SUCCESS;
 }
 
@@ -82,9 +85,50 @@ static vc_status axpy_common(const vc_codec* c, float alpha, const uint64_t* a, 
   return launch_axpy(R, alpha, a, b, out, n, dump, stream);
 }
 
+vc_status vcx_set_stream_config(int block, int vpt, int nt)
+{
+  if (vpt != 2 && vpt != 4) return VC_ERROR_UNSUPPORTED_CODEC;
+  return set_axpy_cfg(block, vpt / 2, nt);
+}
+
+vc_status vcx_get_stream_config(int* block, int* vpt, int* nt)
+{
+  if (!block || !vpt || !nt) return VC_ERROR_INVALID_VALUE;
+  const StreamCfg g = stream_cfg(0, 0);
+  *block = g.block;
+  *vpt = 2 * g.vpt;
+  *nt = g.nt;
+  return VC_SUCCESS;
+}
+
+vc_status vcx_load_tuning(const char* path)
+{
+  if (!path) return VC_ERROR_INVALID_VALUE;
+  FILE* f = fopen(path, "r");
+  if (!f) return VC_ERROR_INVALID_VALUE;
+  char line[256];
+  vc_status st = VC_SUCCESS;
+  while (fgets(line, sizeof line, f)) {
+    int b = 0, v = 0, t = 0;
+    if (sscanf(line, "axpy block=%d vpt=%d nt=%d", &b, &v, &t) == 3) st = set_axpy_cfg(b, v / 2, t);
+  }
+  fclose(f);
+  return st;
+}
+
+static void apply_env_tuning()
+{
+  static bool done = false;
+  if (done) return;
+  done = true;
+  const char* p = getenv("VC_TUNE_CACHE");
+  if (p && *p) (void)vcx_load_tuning(p);
+}
+
 vc_status vc_axpy(const vc_codec* c, float alpha, const uint64_t* a, const uint64_t* b, uint64_t* out, size_t n,
                   hipStream_t stream)
 {
+  apply_env_tuning();
   return axpy_common(c, alpha, a, b, out, n, nullptr, stream);
 }
 

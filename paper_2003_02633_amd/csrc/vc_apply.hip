@@ -1,0 +1,157 @@
+// vc_apply.hip -- fused decode + dense operator apply on the matrix cores (gfx950).
+//
+// For each element e: out[e] (rows x 3) = M (rows x cols) . X_e, X_e[k] = decode(U[e][k]).
+// This is the operator pattern of Alg. (fr_fdiv_comp) -- a small dense operator applied to
+// compressed nodal vectors -- written as one batched GEMM  Out (rows x 3E) = M (rows x K) .
+// [X_1 | ... | X_E] (K x 3E), K = cols, with the right-hand side decoded on the fly.
+//
+// MFMA tiling (v_mfma_f32_16x16x4f32, FP32 in, FP32 accumulate):
+//   * a wave owns 16 elements; their x, y and z components form three 16-column B tiles;
+//   * rows are covered by MT 16-row tiles, so a wave keeps 3 MT accumulators (4 VGPRs each);
+//   * per K-step of 4, lane l decodes exactly one code -- element e0 + l%16, operand row
+//     k = s + KQ (l/16) (the K dimension is permuted so that each lane walks its element's
+//     codes in order) -- and feeds x, y, z straight into the three B fragments;
+//   * M is staged once per workgroup in LDS, transposed (A[k][row]) so the 16 lanes of a
+//     row group read consecutive addresses; rows beyond `rows` are never stored, columns
+//     k >= cols are zero in LDS and their B values are zero.
+// A workgroup is 4 waves (64 elements per step), persistent over the element tiles.
+#include "vc_internal.hpp"
+
+namespace vc {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int APPLY_WAVES = 4;
+constexpr int APPLY_EPW = 16;      // elements per wave
+
+template <class L, int MODE, int MT>
+__global__ __launch_bounds__(64 * APPLY_WAVES) void k_apply(const float* __restrict__ M, int rows, int cols,
+                                                              int KQ, const uint64_t* __restrict__ U,
+                                                              float* __restrict__ out, size_t n_elem, Params P)
+{
+  extern __shared__ float As[];  // [4*KQ][rows], transposed, zero for k >= cols
+  const int KP = 4 * KQ;
+  for (int i = threadIdx.x; i < KP * rows; i += blockDim.x) {
+    const int k = i / rows, r = i - k * rows;
+    As[i] = (k < cols) ? M[(size_t)r * cols + k] : 0.0f;
+  }
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int j = lane & 15;        // column within a tile = element within the wave's 16
+  const int q = lane >> 4;        // K quarter
+  const size_t ntiles = (n_elem + APPLY_EPW - 1) / APPLY_EPW;
+  for (size_t t = (size_t)blockIdx.x * APPLY_WAVES + wave; t < ntiles; t += (size_t)gridDim.x * APPLY_WAVES) {
+    const size_t e = t * APPLY_EPW + j;
+    const bool e_ok = e < n_elem;
+    const uint64_t* Ue = U + (e_ok ? e : 0) * (size_t)cols;
+    f32x4 acc[MT][3];
+#pragma unroll
+    for (int m = 0; m < MT; m++)
+#pragma unroll
+      for (int c = 0; c < 3; c++) acc[m][c] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+
+    for (int s = 0; s < KQ; s++) {
+      const int k = s + KQ * q;
+      float bx = 0.0f, by = 0.0f, bz = 0.0f;
+      if (e_ok && k < cols) decode_vec<L, MODE>(Ue[k], P, bx, by, bz);
+      const float* Ak = As + (size_t)k * rows;
+#pragma unroll
+      for (int m = 0; m < MT; m++) {
+        const int r = 16 * m + j;
+        const float a = Ak[r < rows ? r : rows - 1];
+        acc[m][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bx, acc[m][0], 0, 0, 0);
+        acc[m][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, by, acc[m][1], 0, 0, 0);
+        acc[m][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bz, acc[m][2], 0, 0, 0);
+      }
+    }
+    // D[i][jj] at lane jj + 16 (i/4), register i%4: this lane holds rows 16m + 4q + (0..3) of
+    // element e, for the three components
+    if (e_ok) {
+      float* oe = out + e * (size_t)rows * 3;
+#pragma unroll
+      for (int m = 0; m < MT; m++) {
+#pragma unroll
+        for (int rr = 0; rr < 4; rr++) {
+          const int row = 16 * m + 4 * q + rr;
+          if (row < rows) {
+            oe[3 * row + 0] = acc[m][0][rr];
+            oe[3 * row + 1] = acc[m][1][rr];
+            oe[3 * row + 2] = acc[m][2][rr];
+          }
+        }
+      }
+    }
+  }
+}
+
+template <class L, int MODE, int MT>
+static vc_status apply_mt(const Resolved& R, const float* M, int rows, int cols, const uint64_t* U, float* out,
+                          size_t n_elem, hipStream_t s)
+{
+  const int KQ = (cols + 3) / 4;
+  const size_t lds = (size_t)4 * KQ * rows * sizeof(float);
+  int dev = 0, ncu = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
+  }
+  const size_t ntiles = (n_elem + APPLY_EPW - 1) / APPLY_EPW;
+  size_t grid = (ntiles + APPLY_WAVES - 1) / APPLY_WAVES;
+  const size_t cap = (size_t)ncu * 2;               // two resident workgroups per CU
+  if (grid > cap) grid = cap;
+  if (grid < 1) grid = 1;
+  if (lds > 64 * 1024 &&
+      hipFuncSetAttribute((const void*)k_apply<L, MODE, MT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
+          hipSuccess)
+    return VC_ERROR_HIP;
+  hipLaunchKernelGGL((k_apply<L, MODE, MT>), dim3((unsigned)grid), dim3(64 * APPLY_WAVES), lds, s, M, rows, cols,
+                     KQ, U, out, n_elem, R.P);
+  return launch_status();
+}
+
+template <class L, int MODE>
+static vc_status apply_t(const Resolved& R, const float* M, int rows, int cols, const uint64_t* U, float* out,
+                         size_t n_elem, hipStream_t s)
+{
+  switch ((rows + 15) / 16) {
+#define VC_MT(n) case n: return apply_mt<L, MODE, n>(R, M, rows, cols, U, out, n_elem, s);
+    VC_MT(1) VC_MT(2) VC_MT(3) VC_MT(4) VC_MT(5) VC_MT(6) VC_MT(7) VC_MT(8)
+    VC_MT(9) VC_MT(10) VC_MT(11) VC_MT(12) VC_MT(13) VC_MT(14) VC_MT(15) VC_MT(16)
+#undef VC_MT
+    default: return VC_ERROR_INVALID_VALUE;
+  }
+}
+
+vc_status launch_apply(const Resolved& R, const float* M, int rows, int cols, const uint64_t* U, float* out,
+                       size_t n_elem, hipStream_t s)
+{
+  switch (R.layout * 4 + R.mode) {
+    case 0: return apply_t<L0722, PLAIN>(R, M, rows, cols, U, out, n_elem, s);
+    case 3: return apply_t<L0722, FRAC>(R, M, rows, cols, U, out, n_elem, s);
+    case 4: return apply_t<L0723, PLAIN>(R, M, rows, cols, U, out, n_elem, s);
+    case 8: return apply_t<L0823, PLAIN>(R, M, rows, cols, U, out, n_elem, s);
+    case 12: return apply_t<L1823, PLAIN>(R, M, rows, cols, U, out, n_elem, s);
+    default: return VC_ERROR_UNSUPPORTED_CODEC;
+  }
+}
+
+}  // namespace vc
+
+using namespace vc;
+
+extern "C" vc_status vc_fused_apply(const vc_codec* c, const float* M, int rows, int cols, const uint64_t* U,
+                                    float* out, size_t n_elem, hipStream_t stream)
+{
+  Resolved R;
+  vc_status st = resolve(c, &R);
+  if (st != VC_SUCCESS) return st;
+  if (rows < 1 || rows > 256 || cols < 1 || cols > 256) return VC_ERROR_INVALID_VALUE;
+  // M^T staged in LDS: 4 ceil(cols/4) x rows floats must fit one workgroup's 80 KiB share
+  if ((size_t)4 * ((cols + 3) / 4) * rows * sizeof(float) > 80 * 1024) return VC_ERROR_INVALID_VALUE;
+  if (n_elem == 0) return VC_SUCCESS;
+  if (!M || !U || !out) return VC_ERROR_INVALID_VALUE;
+  if (((uintptr_t)M & 3u) || ((uintptr_t)U & 7u) || ((uintptr_t)out & 3u)) return VC_ERROR_MISALIGNED;
+  return launch_apply(R, M, rows, cols, U, out, n_elem, stream);
+}

@@ -76,9 +76,27 @@ VC_DI float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 VC_DI float log2_(float x) { return __builtin_amdgcn_logf(x); }     // v_log_f32 (log2)
 VC_DI float asin_(float x) { return asinf(x); }
 #endif
+#ifdef VC_HOST_EMULATION
+VC_DI uint64_t dbits(double d) { uint64_t u; memcpy(&u, &d, 8); return u; }
+VC_DI double rsq64_(double x) { return (1.0 / sqrt(x)) * (1.0 + 3e-8); }   // crude, like v_rsq_f64
+VC_DI double rcp64_(double x) { return (1.0 / x) * (1.0 - 4e-8); }
+VC_DI double floor64_(double x) { return floor(x); }
+VC_DI double fma64_(double a, double b, double c) { return fma(a, b, c); }
+#else
+VC_DI uint64_t dbits(double d) { return (uint64_t)__double_as_longlong(d); }
+VC_DI double rsq64_(double x) { return __builtin_amdgcn_rsq(x); }   // v_rsq_f64, ~2^-24
+VC_DI double rcp64_(double x) { return __builtin_amdgcn_rcp(x); }   // v_rcp_f64, ~2^-24
+VC_DI double floor64_(double x) { return __builtin_floor(x); }
+VC_DI double fma64_(double a, double b, double c) { return __builtin_fma(a, b, c); }
+#endif
 VC_DI float fabs_(float x) { return ubits(fbits(x) & 0x7fffffffu); }
-VC_DI float fmax_(float a, float b) { return a > b ? a : b; }
-VC_DI float fmin_(float a, float b) { return a < b ? a : b; }
+#ifdef VC_HOST_EMULATION
+VC_DI float fmax_(float a, float b) { return fmaxf(a, b); }
+VC_DI float fmin_(float a, float b) { return fminf(a, b); }
+#else
+VC_DI float fmax_(float a, float b) { return __builtin_fmaxf(a, b); }
+VC_DI float fmin_(float a, float b) { return __builtin_fminf(a, b); }
+#endif
 VC_DI uint32_t umax3(uint32_t a, uint32_t b, uint32_t c) { uint32_t m = a > b ? a : b; return m > c ? m : c; }
 
 // ------------------------------------------------------------------ layouts
@@ -124,7 +142,15 @@ struct Params {
   float gam, inv_gam, cgam;  // gamma, 1/gamma, tanh(gamma)
   float w[8];                // tanh: h(u)/u - 1 = sum w[i] (u^2)^i (u in [-1,1])
   int wdeg;
+  // FP64-assisted encode
+  int wdeg64;
+  double Kt64, Np64;         // n_theta_max/2, n_phi_max
+  double Ct64, Cp64;         // (n_theta_max/2)/pi, n_phi_max/pi
+  double invKt64, invKc64;   // 1/(n_theta_max/2), 1/(n_phi_max/2)
+  double w64[16];            // tanh: h(u)/u = sum w64[i] (u^2)^i
 };
+
+enum Prec { PREC_F32 = 0, PREC_F64 = 1 };
 
 // ------------------------------------------------------------------ decode
 
@@ -316,15 +342,12 @@ VC_DI void angle_levels(float num_h, float num_l, float den_h, float den_l, bool
   const float Tt = Lh * u;
   const float Hh = Lh + Tt;
   const float Hl = ((Lh - Hh) + Tt) + Ll;
-  // octant offsets: atan2 = [swap] pi/2 +- ([R] pi/4 + atan b); den_neg mirrors about pi/2
-  //   !den_neg, !swap: B = R Kq/2,            s = +1
-  //   !den_neg,  swap: B = Kq - R Kq/2,       s = -1
-  //    den_neg, !swap: B = 2 Kq - R Kq/2,     s = -1
-  //    den_neg,  swap: B = Kq + R Kq/2,       s = +1
+  // octant offset in units of Kq/2: atan2 = [swap] pi/2 +- ([R] pi/4 + atan b), mirrored for den < 0
   const bool neg = den_neg != swap;
-  const float B0 = swap ? Kq : (den_neg ? 2.0f * Kq : 0.0f);
+  const int k0 = swap ? 2 : (den_neg ? 4 : 0);
+  const int kk = neg ? k0 - (int)R : k0 + (int)R;
+  const float B = (float)kk * (0.5f * Kq);        // exact: a multiple of 1/8 below 2^18
   const float sg = neg ? -1.0f : 1.0f;
-  const float B = R ? fma_(sg, 0.5f * Kq, B0) : B0;
   const float sHh = sg * Hh, sHl = sg * Hl;
   // Fast2Sum: |B| >= |H| whenever B != 0
   vh = B + sHh;
@@ -400,9 +423,9 @@ VC_DI void compand_levels(float qh, float ql, float K, const Params& P, float& o
 
 // ------------------------------------------------------------------ encode
 
-// Code of a float32 vector (the compress function of §3).
+// Code of a float32 vector (the compress function of §3), single-precision arithmetic only.
 template <class L, int MODE>
-VC_DI uint64_t encode_vec(float x, float y, float z, const Params& P)
+VC_DI uint64_t encode_vec32(float x, float y, float z, const Params& P)
 {
   const uint32_t ax = fbits(x) & 0x7fffffffu, ay = fbits(y) & 0x7fffffffu, az = fbits(z) & 0x7fffffffu;
   const uint32_t amax = umax3(ax, ay, az);
@@ -513,6 +536,148 @@ VC_DI uint64_t encode_vec(float x, float y, float z, const Params& P)
   if (MODE == FRAC) low = (uint64_t)nph * (uint64_t)P.T + (uint64_t)nth;
   else low = ((uint64_t)nph << L::t) | (uint64_t)nth;
   return ((uint64_t)(uint32_t)E << L::sh_e) | ((uint64_t)Mfield << L::sh_m) | low;
+}
+
+
+// ------------------------------------------------------------------ FP64-assisted encode
+// Same definitions, with the norm, the angle ratios and the level coordinates carried
+// in double precision (the paper's implementation section prescribes double-precision
+// intermediates for phi).  On gfx950 an FP64 FMA costs ~1.3 FP32 FMAs, so this is
+// cheaper than the double-float single-precision path.  The hardware FP64
+// reciprocal/rsqrt are ~2^-24 accurate and get one correction step each.
+
+// Level coordinate of atan2(num, den), num, den >= 0: V = Kq atan2/(pi/2) (den >= 0),
+// 2 Kq - that (den < 0), with C = Kq/(pi/2).
+VC_DI double angle_levels64(double num, double den, bool den_neg, double Kq_half, double C)
+{
+  constexpr double T8 = 0.41421356237309503;      // tan(pi/8)
+  const bool swap = num > den;
+  const double mx = swap ? num : den, mn = swap ? den : num;
+  const bool R = mn > T8 * mx;
+  const double nu = R ? mn - mx : mn;
+  const double de = R ? mn + mx : mx;             // > 0 except at the pole (caller fixes theta there)
+  const double rc = rcp64_(de);
+  double b = nu * rc;
+  b = fma64_(fma64_(-b, de, nu), rc, b);          // quotient to ~2^-48
+  const double s2 = b * b;
+  double Rp = VC_ATAN_R64[VC_ATAN_R64_DEG];
+#pragma unroll
+  for (int i = VC_ATAN_R64_DEG - 1; i >= 0; i--) Rp = fma64_(Rp, s2, VC_ATAN_R64[i]);
+  const double at = fma64_(b, s2 * Rp, b);        // atan(b)
+  // octant offset in units of Kq/2: atan2 = [swap] pi/2 +- ([R] pi/4 + atan b), mirrored for den < 0
+  const bool neg = den_neg != swap;
+  const int k0 = swap ? 2 : (den_neg ? 4 : 0);
+  const int k = neg ? k0 - (int)R : k0 + (int)R;
+  return fma64_(C, neg ? -at : at, (double)k * Kq_half);
+}
+
+// Companded level distance from the centre: K h(q/K) for q = K |u| >= 0.
+template <int MODE>
+VC_DI double compand64(double q, double invK, const Params& P)
+{
+  const double u = q * invK;
+  const double v = u * u;
+  if (MODE == TANH) {                             // h(u)/u = W(u^2), fitted per gamma on the host
+    double acc = P.w64[P.wdeg64];
+    for (int i = P.wdeg64 - 1; i >= 0; i--) acc = fma64_(acc, v, P.w64[i]);
+    return q * acc;
+  }
+  // cosine map: h(u) = sin(pi u / 2) = (pi/2) u S(x^2), x = pi u / 2 (Taylor, |x| <= pi/2)
+  const double x2 = 2.4674011002723395 * v;       // (pi/2)^2 u^2
+  double t = -1.9572941063391263e-20;             // -1/21!
+  t = fma64_(t, x2, 8.2206352466243295e-18);      //  1/19!
+  t = fma64_(t, x2, -2.8114572543455206e-15);     // -1/17!
+  t = fma64_(t, x2, 7.6471637318198164e-13);      //  1/15!
+  t = fma64_(t, x2, -1.6059043836821613e-10);     // -1/13!
+  t = fma64_(t, x2, 2.5052108385441720e-08);      //  1/11!
+  t = fma64_(t, x2, -2.7557319223985888e-06);     // -1/9!
+  t = fma64_(t, x2, 1.9841269841269841e-04);      //  1/7!
+  t = fma64_(t, x2, -8.3333333333333332e-03);     // -1/5!
+  t = fma64_(t, x2, 1.6666666666666666e-01);      //  1/3!
+  const double S = fma64_(-t, x2, 1.0);
+  return q * (1.5707963267948966 * S);
+}
+
+template <class L, int MODE>
+VC_DI uint64_t encode_vec64(float x, float y, float z, const Params& P)
+{
+  const uint32_t ax = fbits(x) & 0x7fffffffu, ay = fbits(y) & 0x7fffffffu, az = fbits(z) & 0x7fffffffu;
+  const uint32_t amax = umax3(ax, ay, az);
+  if (amax >= 0x7f800000u) return L::reserved;    // non-finite input
+  if (amax == 0u) return 0ull;                    // zero vector
+  const double X = (double)x, Y = (double)y, Z = (double)z;   // exact; squares exact in FP64
+  const double R2 = fma64_(X, X, Y * Y);          // rho^2, one rounding
+  const double S = fma64_(Z, Z, R2);              // r^2, two roundings (2^-52)
+
+  // ---- magnitude: r to ~2^-47 (rsqrt seed + one Newton step), nearest-even at 1+m bits
+  const double yS = rsq64_(S);
+  const double r0 = S * yS;
+  const double r = fma64_(fma64_(-r0, r0, S), 0.5 * yS, r0);
+  constexpr int drop = 52 - L::m;                 // fraction bits dropped from the FP64 value
+  constexpr uint32_t half = 1u << (drop - 1);
+  const uint64_t rb0 = dbits(r);
+  const uint32_t low = (uint32_t)rb0 & ((1u << drop) - 1u);
+  bool amb = (low - (half - 256u)) < 512u;        // within 2^-44 of a rounding midpoint
+  const uint64_t rb = (rb0 + half) & ~((1ull << drop) - 1ull);
+  int e_r = (int)(rb >> 52) - 1023;
+  uint32_t Mfield = (uint32_t)(rb >> drop) & ((1u << L::m) - 1u);
+  if (L::keep_sub) amb = amb || (e_r + L::bias <= 1);
+  if (amb) {
+    uint32_t j;
+    int g;
+    exact_norm_round(x, y, z, L::m + 1, L::keep_sub, j, g);
+    if (j >= (1u << L::m)) { e_r = g + L::m; Mfield = j - (1u << L::m); }
+    else { e_r = -L::bias; Mfield = j; }
+  }
+  int E = e_r + L::bias;
+  if (E < 1 && !(L::keep_sub && E == 0)) return 0ull;   // underflow flushes to the zero code
+  if (L::keep_sub && E == 0 && Mfield == 0u) return 0ull;
+  if (E > L::emax) { E = L::emax; Mfield = (1u << L::m) - 1u; }   // saturate
+
+  // ---- rho = sqrt(x^2 + y^2) to ~2^-47 (R2 + 2^-1000 == R2 unless R2 == 0)
+  const double R2g = R2 + 0x1p-1000;
+  const double yR = rsq64_(R2g);
+  const double p0 = R2 * yR;
+  const double rho = fma64_(fma64_(-p0, p0, R2), 0.5 * yR, p0);
+
+  // ---- theta: |Q| = Kt |theta|/pi; n = base + floor(+-|Q| (+1/2 if n_theta_max is even))
+  const bool yneg = y < 0.0f, xneg = x < 0.0f, zneg = z < 0.0f;
+  double Q = angle_levels64(__builtin_fabs(Y), __builtin_fabs(X), xneg, 0.25 * P.Kt64, P.Ct64);
+  if ((MODE == TANH || MODE == COS) && P.comp_t) Q = compand64<MODE>(Q, P.invKt64, P);
+  uint32_t nth;
+  if (MODE == FRAC) {
+    const double Qs = yneg ? -Q : Q;
+    nth = (uint32_t)((int)P.base_t + (int)floor64_(P.odd_t ? Qs : Qs + 0.5));
+  } else {
+    // n_theta_max odd: for y < 0, |Q| is never an integer, so floor(-|Q|) = -1 - floor(|Q|)
+    const int f = (int)floor64_(Q);
+    nth = yneg ? (uint32_t)((int)P.base_t - 1 - f) : (uint32_t)((int)P.base_t + f);
+  }
+  if (R2 == 0.0) nth = P.base_t;                  // pole: theta = atan2(0, 0) = 0
+
+  // ---- phi: V = n_phi_max phi/pi; n = floor(V + 1/2)
+  const double V = angle_levels64(rho, __builtin_fabs(Z), zneg, 0.25 * P.Np64, P.Cp64);
+  uint32_t nph;
+  if ((MODE == TANH || MODE == COS) && P.comp_p) {
+    const double Qc = V - 0.5 * P.Np64;           // (n_phi_max/2) u_phi, exact zero at phi = pi/2
+    const double m = compand64<MODE>(__builtin_fabs(Qc), P.invKc64, P);
+    nph = (uint32_t)((int)((P.nmax_p + 1u) / 2u) + (int)floor64_(Qc < 0 ? -m : m));
+  } else {
+    nph = (uint32_t)(int)floor64_(V + 0.5);
+  }
+
+  uint64_t lowf;
+  if (MODE == FRAC) lowf = (uint64_t)nph * (uint64_t)P.T + (uint64_t)nth;
+  else lowf = ((uint64_t)nph << L::t) | (uint64_t)nth;
+  return ((uint64_t)(uint32_t)E << L::sh_e) | ((uint64_t)Mfield << L::sh_m) | lowf;
+}
+
+// precision dispatch
+template <class L, int MODE, int PREC>
+VC_DI uint64_t encode_vec(float x, float y, float z, const Params& P)
+{
+  if constexpr (PREC == PREC_F64) return encode_vec64<L, MODE>(x, y, z, P);
+  else return encode_vec32<L, MODE>(x, y, z, P);
 }
 
 }  // namespace vc

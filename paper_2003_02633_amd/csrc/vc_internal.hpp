@@ -11,13 +11,14 @@
 
 namespace vc {
 
-// tuning knobs of the streaming kernels (autotuned; see tune.cpp)
+// launch configuration of the streaming axpy (chosen by the autotuner, paper_2003_02633_amd/tune.py)
 struct StreamCfg {
   int block;       // threads per block
-  int vpt;         // vectors per thread and iteration
+  int vpt;         // vectors per thread and grid step (2 or 4)
   int nt;          // non-temporal loads/stores
 };
 StreamCfg stream_cfg(int op, size_t n);
+vc_status set_axpy_cfg(int block, int vpt, int nt);
 
 vc_status launch_encode(const Resolved& R, const float* xyz, uint64_t* codes, size_t n, hipStream_t s);
 vc_status launch_decode(const Resolved& R, const uint64_t* codes, float* xyz, size_t n, hipStream_t s);
@@ -28,6 +29,8 @@ vc_status launch_dot(const Resolved& R, const uint64_t* a, const uint64_t* b, si
 vc_status launch_norm2(const Resolved& R, const uint64_t* a, size_t n, float* partials, int nparts,
                        float* d_out, hipStream_t s);
 int reduce_parts(size_t n);
+vc_status launch_apply(const Resolved& R, const float* M, int rows, int cols, const uint64_t* U, float* out,
+                       size_t n_elem, hipStream_t s);
 
 inline vc_status launch_status()
 {

@@ -16,6 +16,7 @@ struct Resolved {
   int layout;      // vc_layout
   int mode;        // vc::Mode
   int mag_round;   // vc_mag_round
+  int prec;        // vc::Prec
   Params P;
 };
 
@@ -102,6 +103,60 @@ static inline double fit_tanh_tail(double gamma, float* w, int deg)
   return maxerr;
 }
 
+// W(v) = tanh(gamma sqrt v)/(tanh(gamma) sqrt v) on v in [0, 1]: h(u)/u of the tanh
+// companding map (u^2 = v).
+static inline long double tanh_ratio(long double gamma, long double v)
+{
+  const long double c = tanhl(gamma);
+  const long double u = sqrtl(v);
+  if (u < 1e-7L) return gamma / c * (1.0L - gamma * gamma * v / 3.0L);
+  return tanhl(gamma * u) / (c * u);
+}
+
+// Chebyshev projection of W on [0, 1] (128 nodes, long double), truncated at `deg` and
+// converted to monomial coefficients in v.  Returns the max residual of the double
+// coefficients on a fine grid.
+static inline double fit_tanh_ratio64(double gamma, double* w, int deg)
+{
+  const int M = 128;
+  long double a[20] = {0};
+  for (int k = 0; k <= deg; k++) {
+    long double sacc = 0.0L;
+    for (int j = 0; j < M; j++) {
+      const long double th = 3.14159265358979323846264338327950288L * (j + 0.5L) / M;
+      const long double t = cosl(th);
+      sacc += tanh_ratio(gamma, 0.5L * (t + 1.0L)) * cosl(k * th);
+    }
+    a[k] = sacc * 2.0L / M;
+  }
+  a[0] *= 0.5L;
+  // sum a_k T_k(t), t = 2v - 1  ->  monomials in v
+  long double Tkm1[20] = {0}, Tk[20] = {0}, Tkp1[20], mono[20] = {0};
+  Tkm1[0] = 1.0L;                       // T_0 = 1
+  Tk[0] = -1.0L; Tk[1] = 2.0L;          // T_1 = 2v - 1
+  for (int i = 0; i <= deg; i++) mono[i] += a[0] * Tkm1[i];
+  if (deg >= 1) for (int i = 0; i <= deg; i++) mono[i] += a[1] * Tk[i];
+  for (int k = 2; k <= deg; k++) {
+    // T_{k} = 2 t T_{k-1} - T_{k-2} = (4v - 2) T_{k-1} - T_{k-2}
+    for (int i = 0; i <= deg; i++) {
+      long double vprev = i ? Tk[i - 1] : 0.0L;
+      Tkp1[i] = 4.0L * vprev - 2.0L * Tk[i] - Tkm1[i];
+    }
+    for (int i = 0; i <= deg; i++) { Tkm1[i] = Tk[i]; Tk[i] = Tkp1[i]; }
+    for (int i = 0; i <= deg; i++) mono[i] += a[k] * Tk[i];
+  }
+  for (int i = 0; i <= deg; i++) w[i] = (double)mono[i];
+  double maxerr = 0.0;
+  for (int k = 0; k <= 4000; k++) {
+    const long double u = k / 4000.0L, v = u * u;
+    long double acc = w[deg];
+    for (int i = deg - 1; i >= 0; i--) acc = acc * v + w[i];
+    const double e = (double)fabsl(acc - tanh_ratio(gamma, v));
+    if (e > maxerr) maxerr = e;
+  }
+  return maxerr;
+}
+
 inline vc_status resolve(const vc_codec* c, Resolved* R)
 {
   if (!c || !R) return VC_ERROR_INVALID_VALUE;
@@ -109,11 +164,13 @@ inline vc_status resolve(const vc_codec* c, Resolved* R)
   if (c->layout > VC_LAYOUT_1_8_23_16_16) return VC_ERROR_UNSUPPORTED_CODEC;
   if (c->mode > VC_MODE_FRACSPLIT) return VC_ERROR_UNSUPPORTED_CODEC;
   if (c->mag_round != VC_MAG_RNE) return VC_ERROR_UNSUPPORTED_CODEC;   // truncation: oracle-only
+  if (c->precision > VC_PREC_F32 || c->reserved0 != 0) return VC_ERROR_INVALID_VALUE;
   if (c->mode != VC_MODE_PLAIN && c->layout != VC_LAYOUT_0_7_22_17_18) return VC_ERROR_UNSUPPORTED_CODEC;
   memset(R, 0, sizeof(*R));
   R->layout = (int)c->layout;
   R->mode = (int)c->mode;
   R->mag_round = (int)c->mag_round;
+  R->prec = c->precision == VC_PREC_F32 ? PREC_F32 : PREC_F64;
   Params& P = R->P;
   const LayoutBits lb = layout_bits((int)c->layout);
   uint64_t nt, np;
@@ -144,18 +201,32 @@ inline vc_status resolve(const vc_codec* c, Resolved* R)
   split_dd((long double)np / PI, &P.Cp_h, &P.Cp_l);
   split_dd(1.0L / (long double)nt, &P.rt_h, &P.rt_l);
   split_dd(1.0L / (2.0L * (long double)np), &P.rp_h, &P.rp_l);
+  P.Kt64 = (double)nt / 2.0;
+  P.Np64 = (double)np;
+  P.Ct64 = (double)((long double)nt / 2.0L / PI);
+  P.Cp64 = (double)((long double)np / PI);
+  P.invKt64 = (double)(2.0L / (long double)nt);
+  P.invKc64 = (double)(2.0L / (long double)np);
   if (c->mode == VC_MODE_TANH || c->mode == VC_MODE_COS) {
     P.comp_t = (c->compand_mask & VC_COMPAND_THETA) ? 1u : 0u;
     P.comp_p = (c->compand_mask & VC_COMPAND_PHI) ? 1u : 0u;
   }
   if (c->mode == VC_MODE_TANH) {
-    if (!(c->gamma > 0.0f) || c->gamma > 1.5f) return VC_ERROR_UNSUPPORTED_CODEC;
+    if (!(c->gamma > 0.0f) || c->gamma > 1.0f) return VC_ERROR_UNSUPPORTED_CODEC;
     P.gam = c->gamma;
     P.inv_gam = 1.0f / c->gamma;
     P.cgam = (float)tanh((double)c->gamma);
     P.wdeg = 7;
     const double err = fit_tanh_tail((double)c->gamma, P.w, P.wdeg);
     if (err > 2e-8) return VC_ERROR_UNSUPPORTED_CODEC;   // residual relative to |Q| scales like the 1-ulp window
+    // smallest degree whose double-precision fit is within 1e-14 (the level error near the
+    // phi poles is Kc times this residual)
+    double err64 = 1.0;
+    for (P.wdeg64 = 6; P.wdeg64 <= 15; P.wdeg64++) {
+      err64 = fit_tanh_ratio64((double)c->gamma, P.w64, P.wdeg64);
+      if (err64 <= 1e-14) break;
+    }
+    if (err64 > 1e-14) return VC_ERROR_UNSUPPORTED_CODEC;
   }
   return VC_SUCCESS;
 }

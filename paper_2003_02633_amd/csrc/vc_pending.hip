@@ -4,11 +4,6 @@
 
 extern "C" {
 
-vc_status vc_fused_apply(const vc_codec*, const float*, int, int, const uint64_t*, float*, size_t, hipStream_t)
-{
-  return VC_ERROR_UNSUPPORTED_CODEC;
-}
-
 vc_status vc_batch_plan_create(vc_batch_plan** plan, const vc_codec*, const vc_segment*, int, hipStream_t)
 {
   if (plan) *plan = nullptr;

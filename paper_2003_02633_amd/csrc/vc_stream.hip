@@ -7,6 +7,8 @@
 //   k_encode : float32 AoS -> codes                        -- compress(), §3
 //   k_decode : codes -> float32 AoS                        -- decompress(), Alg. (fr_fdiv_comp)
 //   k_dot / k_norm2 : FP32 reductions over decoded vectors
+#include <type_traits>
+
 #include "vc_internal.hpp"
 
 namespace vc {
@@ -31,7 +33,7 @@ __device__ __forceinline__ void st(T* p, T v)
 // Each lane handles U pairs of consecutive codes per grid step; pair u of a
 // block lives at [blk + u*2*BS + 2*tid, +2), so every load/store instruction of
 // a wave covers 1 KiB contiguous.
-template <class L, int MODE, int BS, int U, bool NT, bool DUMP>
+template <class L, int MODE, int PREC, int BS, int U, bool NT, bool DUMP>
 __global__ __launch_bounds__(BS) void k_axpy(const uint64_t* __restrict__ a, const uint64_t* __restrict__ b,
                                              uint64_t* __restrict__ c, size_t n, size_t ntiles, float alpha,
                                              Params P, float* __restrict__ dump)
@@ -61,7 +63,7 @@ __global__ __launch_bounds__(BS) void k_axpy(const uint64_t* __restrict__ a, con
           const size_t i = base + (size_t)u * 2 * BS + h;
           dump[3 * i] = cx; dump[3 * i + 1] = cy; dump[3 * i + 2] = cz;
         }
-        out[h] = encode_vec<L, MODE>(cx, cy, cz, P);
+        out[h] = encode_vec<L, MODE, PREC>(cx, cy, cz, P);
       }
       st<NT>((u64x2*)(c + base + (size_t)u * 2 * BS), out);
     }
@@ -76,7 +78,7 @@ __global__ __launch_bounds__(BS) void k_axpy(const uint64_t* __restrict__ a, con
     const float cy = __builtin_fmaf(alpha, ay, by);
     const float cz = __builtin_fmaf(alpha, az, bz);
     if constexpr (DUMP) { dump[3 * i] = cx; dump[3 * i + 1] = cy; dump[3 * i + 2] = cz; }
-    c[i] = encode_vec<L, MODE>(cx, cy, cz, P);
+    c[i] = encode_vec<L, MODE, PREC>(cx, cy, cz, P);
   }
 }
 
@@ -84,7 +86,7 @@ __global__ __launch_bounds__(BS) void k_axpy(const uint64_t* __restrict__ a, con
 // Groups of 4 vectors per lane: 48 bytes of float32 AoS (3 x 16-byte accesses)
 // and 32 bytes of codes (2 x 16-byte accesses).  Requires 16-byte aligned
 // pointers (checked by the launcher, which otherwise uses the scalar kernel).
-template <class L, int MODE, int BS, bool NT>
+template <class L, int MODE, int PREC, int BS, bool NT>
 __global__ __launch_bounds__(BS) void k_encode4(const float* __restrict__ xyz, uint64_t* __restrict__ codes,
                                                 size_t n, Params P)
 {
@@ -93,24 +95,24 @@ __global__ __launch_bounds__(BS) void k_encode4(const float* __restrict__ xyz, u
     const f32x4* src = (const f32x4*)(xyz + 12 * g);
     const f32x4 q0 = ld<NT>(src), q1 = ld<NT>(src + 1), q2 = ld<NT>(src + 2);
     u64x2 o0, o1;
-    o0[0] = encode_vec<L, MODE>(q0[0], q0[1], q0[2], P);
-    o0[1] = encode_vec<L, MODE>(q0[3], q1[0], q1[1], P);
-    o1[0] = encode_vec<L, MODE>(q1[2], q1[3], q2[0], P);
-    o1[1] = encode_vec<L, MODE>(q2[1], q2[2], q2[3], P);
+    o0[0] = encode_vec<L, MODE, PREC>(q0[0], q0[1], q0[2], P);
+    o0[1] = encode_vec<L, MODE, PREC>(q0[3], q1[0], q1[1], P);
+    o1[0] = encode_vec<L, MODE, PREC>(q1[2], q1[3], q2[0], P);
+    o1[1] = encode_vec<L, MODE, PREC>(q2[1], q2[2], q2[3], P);
     u64x2* dst = (u64x2*)(codes + 4 * g);
     st<NT>(dst, o0);
     st<NT>(dst + 1, o1);
   }
   for (size_t i = 4 * ng + (size_t)blockIdx.x * BS + threadIdx.x; i < n; i += (size_t)gridDim.x * BS)
-    codes[i] = encode_vec<L, MODE>(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], P);
+    codes[i] = encode_vec<L, MODE, PREC>(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], P);
 }
 
-template <class L, int MODE, int BS>
+template <class L, int MODE, int PREC, int BS>
 __global__ __launch_bounds__(BS) void k_encode1(const float* __restrict__ xyz, uint64_t* __restrict__ codes,
                                                 size_t n, Params P)
 {
   for (size_t i = (size_t)blockIdx.x * BS + threadIdx.x; i < n; i += (size_t)gridDim.x * BS)
-    codes[i] = encode_vec<L, MODE>(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], P);
+    codes[i] = encode_vec<L, MODE, PREC>(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], P);
 }
 
 template <class L, int MODE, int BS, bool NT>
@@ -208,40 +210,84 @@ static inline unsigned grid_for(size_t work, size_t per_block, unsigned cap)
   return (unsigned)g;
 }
 
-template <class L, int MODE>
-static vc_status axpy_t(const Resolved& R, float alpha, const uint64_t* a, const uint64_t* b, uint64_t* c,
-                        size_t n, float* dump, hipStream_t s)
+// ---- launch configuration of the streaming axpy (set by the autotuner, see vcx_set_stream_config)
+static StreamCfg g_axpy_cfg = {256, 1, 1};
+
+StreamCfg stream_cfg(int op, size_t)
 {
-  constexpr int BS = 256, U = 1;
+  (void)op;
+  return g_axpy_cfg;
+}
+
+vc_status set_axpy_cfg(int block, int vpt, int nt)
+{
+  const bool okb = block == 128 || block == 256 || block == 512;
+  const bool oku = vpt == 1 || vpt == 2;   // grid steps of 2 codes per lane
+  if (!okb || !oku || (nt != 0 && nt != 1)) return VC_ERROR_UNSUPPORTED_CODEC;
+  g_axpy_cfg = {block, vpt, nt};
+  return VC_SUCCESS;
+}
+
+template <class L, int MODE, int PREC, int BS, int U, bool NT>
+static vc_status axpy_launch(const Resolved& R, float alpha, const uint64_t* a, const uint64_t* b, uint64_t* c,
+                             size_t n, float* dump, hipStream_t s)
+{
   constexpr size_t TILE = (size_t)2 * BS * U;
   const bool aligned = (((uintptr_t)a | (uintptr_t)b | (uintptr_t)c) & 15u) == 0;
   const size_t ntiles = aligned ? n / TILE : 0;
   const unsigned grid = grid_for(n, TILE, 1u << 30);
   if (dump)
-    hipLaunchKernelGGL((k_axpy<L, MODE, BS, U, false, true>), dim3(grid), dim3(BS), 0, s, a, b, c, n, ntiles,
+    hipLaunchKernelGGL((k_axpy<L, MODE, PREC, BS, U, false, true>), dim3(grid), dim3(BS), 0, s, a, b, c, n, ntiles,
                        alpha, R.P, dump);
   else
-    hipLaunchKernelGGL((k_axpy<L, MODE, BS, U, true, false>), dim3(grid), dim3(BS), 0, s, a, b, c, n, ntiles,
+    hipLaunchKernelGGL((k_axpy<L, MODE, PREC, BS, U, NT, false>), dim3(grid), dim3(BS), 0, s, a, b, c, n, ntiles,
                        alpha, R.P, dump);
   return launch_status();
 }
 
-template <class L, int MODE>
+template <class L, int MODE, int PREC>
+static vc_status axpy_t(const Resolved& R, float alpha, const uint64_t* a, const uint64_t* b, uint64_t* c,
+                        size_t n, float* dump, hipStream_t s)
+{
+  // tuned variants for the default layout and uniform quantisation; other codecs use 256 x 1, NT
+  if constexpr (std::is_same<L, L0722>::value && MODE == PLAIN) {
+    const StreamCfg g = g_axpy_cfg;
+    const int key = (g.block == 128 ? 0 : g.block == 256 ? 1 : 2) * 4 + (g.vpt == 2 ? 2 : 0) + g.nt;
+    switch (key) {
+      case 0: return axpy_launch<L, MODE, PREC, 128, 1, false>(R, alpha, a, b, c, n, dump, s);
+      case 1: return axpy_launch<L, MODE, PREC, 128, 1, true>(R, alpha, a, b, c, n, dump, s);
+      case 2: return axpy_launch<L, MODE, PREC, 128, 2, false>(R, alpha, a, b, c, n, dump, s);
+      case 3: return axpy_launch<L, MODE, PREC, 128, 2, true>(R, alpha, a, b, c, n, dump, s);
+      case 4: return axpy_launch<L, MODE, PREC, 256, 1, false>(R, alpha, a, b, c, n, dump, s);
+      case 5: return axpy_launch<L, MODE, PREC, 256, 1, true>(R, alpha, a, b, c, n, dump, s);
+      case 6: return axpy_launch<L, MODE, PREC, 256, 2, false>(R, alpha, a, b, c, n, dump, s);
+      case 7: return axpy_launch<L, MODE, PREC, 256, 2, true>(R, alpha, a, b, c, n, dump, s);
+      case 8: return axpy_launch<L, MODE, PREC, 512, 1, false>(R, alpha, a, b, c, n, dump, s);
+      case 9: return axpy_launch<L, MODE, PREC, 512, 1, true>(R, alpha, a, b, c, n, dump, s);
+      case 10: return axpy_launch<L, MODE, PREC, 512, 2, false>(R, alpha, a, b, c, n, dump, s);
+      default: return axpy_launch<L, MODE, PREC, 512, 2, true>(R, alpha, a, b, c, n, dump, s);
+    }
+  } else {
+    return axpy_launch<L, MODE, PREC, 256, 1, true>(R, alpha, a, b, c, n, dump, s);
+  }
+}
+
+template <class L, int MODE, int PREC>
 static vc_status encode_t(const Resolved& R, const float* xyz, uint64_t* codes, size_t n, hipStream_t s)
 {
   constexpr int BS = 256;
   const bool aligned = (((uintptr_t)xyz | (uintptr_t)codes) & 15u) == 0;
   if (aligned) {
     const unsigned grid = grid_for(n, (size_t)4 * BS, 1u << 30);
-    hipLaunchKernelGGL((k_encode4<L, MODE, BS, true>), dim3(grid), dim3(BS), 0, s, xyz, codes, n, R.P);
+    hipLaunchKernelGGL((k_encode4<L, MODE, PREC, BS, true>), dim3(grid), dim3(BS), 0, s, xyz, codes, n, R.P);
   } else {
     const unsigned grid = grid_for(n, (size_t)BS, 1u << 30);
-    hipLaunchKernelGGL((k_encode1<L, MODE, BS>), dim3(grid), dim3(BS), 0, s, xyz, codes, n, R.P);
+    hipLaunchKernelGGL((k_encode1<L, MODE, PREC, BS>), dim3(grid), dim3(BS), 0, s, xyz, codes, n, R.P);
   }
   return launch_status();
 }
 
-template <class L, int MODE>
+template <class L, int MODE, int PREC>
 static vc_status decode_t(const Resolved& R, const uint64_t* codes, float* xyz, size_t n, hipStream_t s)
 {
   constexpr int BS = 256;
@@ -264,7 +310,7 @@ int reduce_parts(size_t n)
   return (int)g;
 }
 
-template <class L, int MODE>
+template <class L, int MODE, int PREC>
 static vc_status dot_t(const Resolved& R, const uint64_t* a, const uint64_t* b, size_t n, float* parts, int np,
                        float* out, hipStream_t s)
 {
@@ -285,17 +331,33 @@ static vc_status norm2_t(const uint64_t* a, size_t n, float* parts, int np, floa
   return launch_status();
 }
 
-// layout x mode dispatch
+// layout x mode x precision dispatch (decode-only paths ignore the precision)
+#define VC_CASES(FN, PR, ...)                                                             \
+  case 0: return FN<L0722, PLAIN, PR>(__VA_ARGS__);                                       \
+  case 1: return FN<L0722, TANH, PR>(__VA_ARGS__);                                        \
+  case 2: return FN<L0722, COS, PR>(__VA_ARGS__);                                         \
+  case 3: return FN<L0722, FRAC, PR>(__VA_ARGS__);                                        \
+  case 4: return FN<L0723, PLAIN, PR>(__VA_ARGS__);                                       \
+  case 8: return FN<L0823, PLAIN, PR>(__VA_ARGS__);                                       \
+  case 12: return FN<L1823, PLAIN, PR>(__VA_ARGS__);
 #define VC_DISPATCH(R, FN, ...)                                                           \
   do {                                                                                    \
+    if ((R).prec == PREC_F64) {                                                           \
+      switch ((R).layout * 4 + (R).mode) {                                                \
+        VC_CASES(FN, PREC_F64, __VA_ARGS__)                                               \
+        default: return VC_ERROR_UNSUPPORTED_CODEC;                                       \
+      }                                                                                   \
+    } else {                                                                              \
+      switch ((R).layout * 4 + (R).mode) {                                                \
+        VC_CASES(FN, PREC_F32, __VA_ARGS__)                                               \
+        default: return VC_ERROR_UNSUPPORTED_CODEC;                                       \
+      }                                                                                   \
+    }                                                                                     \
+  } while (0)
+#define VC_DISPATCH_NOPREC(R, FN, ...)                                                    \
+  do {                                                                                    \
     switch ((R).layout * 4 + (R).mode) {                                                  \
-      case 0: return FN<L0722, PLAIN>(__VA_ARGS__);                                       \
-      case 1: return FN<L0722, TANH>(__VA_ARGS__);                                        \
-      case 2: return FN<L0722, COS>(__VA_ARGS__);                                         \
-      case 3: return FN<L0722, FRAC>(__VA_ARGS__);                                        \
-      case 4: return FN<L0723, PLAIN>(__VA_ARGS__);                                       \
-      case 8: return FN<L0823, PLAIN>(__VA_ARGS__);                                       \
-      case 12: return FN<L1823, PLAIN>(__VA_ARGS__);                                      \
+      VC_CASES(FN, PREC_F32, __VA_ARGS__)                                                 \
       default: return VC_ERROR_UNSUPPORTED_CODEC;                                         \
     }                                                                                     \
   } while (0)
@@ -313,13 +375,13 @@ vc_status launch_encode(const Resolved& R, const float* xyz, uint64_t* codes, si
 
 vc_status launch_decode(const Resolved& R, const uint64_t* codes, float* xyz, size_t n, hipStream_t s)
 {
-  VC_DISPATCH(R, decode_t, R, codes, xyz, n, s);
+  VC_DISPATCH_NOPREC(R, decode_t, R, codes, xyz, n, s);
 }
 
 vc_status launch_dot(const Resolved& R, const uint64_t* a, const uint64_t* b, size_t n, float* parts, int np,
                      float* out, hipStream_t s)
 {
-  VC_DISPATCH(R, dot_t, R, a, b, n, parts, np, out, s);
+  VC_DISPATCH_NOPREC(R, dot_t, R, a, b, n, parts, np, out, s);
 }
 
 vc_status launch_norm2(const Resolved& R, const uint64_t* a, size_t n, float* parts, int np, float* out,

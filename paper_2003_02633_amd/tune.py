@@ -1,0 +1,85 @@
+"""Autotuner for the streaming compressed axpy (block size, vectors per thread, non-temporal).
+
+Sweeps every launch configuration the library is built with on a workload of N vectors
+(default 2^27, the benchmark size), checks that all configurations produce bit-identical
+codes, and writes the fastest one as a tuning cache:
+
+    axpy block=<B> vpt=<V> nt=<T>
+
+The library applies the file named by $VC_TUNE_CACHE on first use, and
+``vcx_load_tuning(path)`` applies any cache explicitly.
+
+Usage (on the GPU):  python -m paper_2003_02633_amd.tune [--n N] [--out FILE] [--precision f64|f32]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+
+DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning", "mi355x_axpy.txt")
+CONFIGS = [(b, v, t) for b in (128, 256, 512) for v in (2, 4) for t in (1, 0)]
+
+
+def sweep(n: int = 1 << 27, precision: str = "f64", steps: int = 10, warmup: int = 2, log=print):
+    import torch
+
+    import paper_2003_02633_amd as vc
+    from paper_2003_02633_amd import inputs
+
+    c = vc.codec(precision=precision)
+    a = vc.vc_encode(c, inputs.sphere_loguniform_torch(n, 0))
+    b = vc.vc_encode(c, inputs.sphere_loguniform_torch(n, 1))
+    out = torch.empty_like(a)
+    ref = None
+    results = []
+    saved = vc.get_stream_config()
+    try:
+        for (blk, vpt, nt) in CONFIGS:
+            vc.set_stream_config(blk, vpt, nt)
+            for _ in range(warmup):
+                vc.vc_axpy(c, 0.7, a, b, out)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(steps):
+                vc.vc_axpy(c, 0.7, a, b, out)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            chk = out[:: max(1, n // (1 << 20))].clone()
+            if ref is None:
+                ref = chk
+            same = bool(torch.equal(chk, ref))
+            results.append({"block": blk, "vpt": vpt, "nt": nt, "ms": ms, "gvecs": n / ms / 1e6, "identical": same})
+            log(f"[tune] block={blk} vpt={vpt} nt={nt}: {ms:.4f} ms  {n / ms / 1e6:.1f} Gvec/s  identical={same}")
+    finally:
+        vc.set_stream_config(*saved)
+    if not all(r["identical"] for r in results):
+        raise RuntimeError("launch configurations disagree")
+    return results
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--n", type=int, default=1 << 27)
+    ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--out", default=DEFAULT_CACHE)
+    ap.add_argument("--json", default=None, help="also write all timings here")
+    args = ap.parse_args()
+    res = sweep(args.n, args.precision, log=lambda m: print(m, file=sys.stderr, flush=True))
+    best = min(res, key=lambda r: r["ms"])
+    os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
+    with open(args.out, "w") as f:
+        f.write(f"# compressed axpy launch configuration, N={args.n}, encoder {args.precision}, "
+                f"{best['gvecs']:.1f} Gvec/s\n")
+        f.write(f"axpy block={best['block']} vpt={best['vpt']} nt={best['nt']}\n")
+    if args.json:
+        with open(args.json, "w") as f:
+            json.dump({"n": args.n, "precision": args.precision, "results": res, "best": best}, f, indent=1)
+    print(json.dumps({"best": best}), flush=True)
+
+
+if __name__ == "__main__":
+    main()

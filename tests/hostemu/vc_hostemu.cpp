@@ -12,9 +12,11 @@
 using namespace vc;
 
 template <class L, int MODE>
-static void enc(const Params& P, const float* xyz, uint64_t* out, size_t n)
+static void enc(const Params& P, int prec, const float* xyz, uint64_t* out, size_t n)
 {
-  for (size_t i = 0; i < n; i++) out[i] = encode_vec<L, MODE>(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], P);
+  for (size_t i = 0; i < n; i++)
+    out[i] = prec == PREC_F64 ? encode_vec<L, MODE, PREC_F64>(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], P)
+                              : encode_vec<L, MODE, PREC_F32>(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], P);
 }
 template <class L, int MODE>
 static void dec(const Params& P, const uint64_t* w, float* out, size_t n)
@@ -41,7 +43,7 @@ int emu_encode(const vc_codec* c, const float* xyz, uint64_t* out, size_t n)
   Resolved R;
   vc_status st = resolve(c, &R);
   if (st != VC_SUCCESS) return st;
-  EMU_DISPATCH(R, enc, R.P, xyz, out, n);
+  EMU_DISPATCH(R, enc, R.P, R.prec, xyz, out, n);
   return 0;
 }
 
