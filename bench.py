@@ -133,6 +133,67 @@ def sample_error(torch, wa, wb, wc, nsample: int = 1 << 20, seed: int = 5):
             "sample": int(idx.numel())}
 
 
+def bench_apply(torch, vc, inputs, k: int):
+    """Fused decode + operator apply: 200,000 p = 4 hexahedral elements (125 solution points
+    each) of a Taylor-Green velocity field, operator 150 x 125 with entries U[-1, 1]."""
+    import numpy as np
+
+    E, rows, cols = 200_000, 150, 125
+    c = vc.codec()
+    vel = inputs.tgv_elements(E, 4, seed=0)
+    U = vc.vc_encode(c, torch.from_numpy(vel.reshape(-1, 3)).to("cuda"))
+    del vel
+    M = torch.from_numpy(inputs.uniform_matrix(rows, cols, 2)).to("cuda")
+    out = torch.empty((E, rows, 3), dtype=torch.float32, device="cuda")
+    ms = timed(torch, lambda: vc.vc_fused_apply(c, M, U.view(E, cols), out), k, 2)
+    flop = 2.0 * rows * cols * 3 * E
+    byts = 8.0 * cols * E + 12.0 * rows * E
+    del U, M, out
+    return {"elements": E, "rows": rows, "cols": cols, "ms": ms, "TFLOPs": flop / (ms * 1e-3) / 1e12,
+            "frac_fp32_mfma_peak": flop / (ms * 1e-3) / 157.3e12, "GBs": byts / (ms * 1e-3) / 1e9,
+            "bound": "mfma", "mfma_floor_us": flop / 157.3e12 * 1e6, "hbm_floor_us": byts / 8e12 * 1e6}
+
+
+BYTES_PER_VEC = {"axpy": 24, "dot": 16, "norm2": 8, "encode": 20}
+
+
+def bench_batch(torch, vc, inputs, k: int, precision: str):
+    """64 segments of lengths floor(10^U[3, 7]) (seed 3), a shuffled round robin of axpy (alpha
+    0.7), dot, norm2 and encode: one persistent graph-replayed kernel vs separate launches vs
+    separate launches captured in one graph."""
+    lengths, ops = inputs.segments(nseg=64, seed=3, lo_exp=3.0, hi_exp=7.0)
+    c = vc.codec(precision=precision)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(3)
+    segs, algo = [], 0.0
+    for n, op in zip(lengths, ops):
+        n = int(n)
+        x = torch.randn((n, 3), generator=g, dtype=torch.float32, device="cuda")
+        if op == "encode":
+            segs.append({"op": op, "n": n, "a": x, "out": torch.empty(n, dtype=torch.int64, device="cuda")})
+        else:
+            a = vc.vc_encode(c, x)
+            b = vc.vc_encode(c, torch.randn((n, 3), generator=g, dtype=torch.float32, device="cuda")) \
+                if op in ("axpy", "dot") else None
+            out = torch.empty(n, dtype=torch.int64, device="cuda") if op == "axpy" else \
+                torch.empty(1, dtype=torch.float32, device="cuda")
+            segs.append({"op": op, "n": n, "a": a, "b": b, "out": out, "alpha": ALPHA})
+        del x
+        algo += BYTES_PER_VEC[op] * n
+    torch.cuda.synchronize()
+    plan = vc.BatchPlan(c, segs)
+    tiles, grid = plan.info()
+    res = {"segments": len(segs), "vectors": int(sum(int(n) for n in lengths)), "tiles": tiles, "grid": grid,
+           "algorithmic_bytes": algo}
+    for name, fn in (("persistent_graph", plan.run), ("separate_launches", plan.run_separate),
+                     ("separate_launches_graph", plan.run_separate_graph)):
+        ms = timed(torch, fn, k, 2)
+        res[name] = {"ms": ms, "GBs": algo / (ms * 1e-3) / 1e9}
+    plan.close()
+    del segs
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -264,6 +325,12 @@ def main():
             log(f"variant {name}: {msv:.3f} ms")
             del va_, vb_
         extras["variants_axpy"] = var
+        log("fused apply (200,000 elements, 150 x 125)")
+        extras["fused_apply"] = bench_apply(torch, vc, inputs, k)
+        log(f"fused apply: {extras['fused_apply']}")
+        log("batched segments (64 segments, 10^3..10^7 vectors)")
+        extras["batch"] = bench_batch(torch, vc, inputs, k, args.precision)
+        log(f"batch: {extras['batch']}")
         extras["paper_titanv_speedup_context"] = 1.5
         torch.cuda.synchronize()
         # restore the plain result for consistency

@@ -146,17 +146,24 @@ typedef struct {
 
 typedef struct vc_batch_plan vc_batch_plan;
 
-/* Build a plan for `nseg` segments (host array, copied).  Allocates the device segment
- * table, tile table and reduction scratch, and captures one persistent kernel plus its
- * reduction kernel into a HIP graph.  Synchronises `stream` once.  The plan owns these
- * resources until vc_batch_plan_destroy. */
+/* Build a plan for `nseg` segments (host array, copied; 0 <= nseg <= 2^20).  Each segment is
+ * cut into tiles of 512 vectors; one persistent kernel walks all tiles of all segments with a
+ * static grid stride, and a second kernel sums the per-tile partials of each dot/norm2
+ * segment in a fixed order (deterministic; an empty reduction segment yields 0).  Both are
+ * captured into a HIP graph.  Segments run concurrently, so no segment may write memory that
+ * another segment reads or writes (VC_ERROR_OVERLAP); within a segment the rules of the
+ * single-call entry points hold (axpy may run in place).  Pointer and size checks as for
+ * those entry points.  Allocates the device segment table and partial-sum scratch and
+ * synchronises `stream` once; the plan owns them until vc_batch_plan_destroy.  Segment data
+ * pointers are stored, not copied: they must stay valid while the plan is run. */
 vc_status vc_batch_plan_create(vc_batch_plan** plan, const vc_codec* c, const vc_segment* segs, int nseg,
                                hipStream_t stream);
-/* Replay the plan's graph on `stream` (asynchronous). */
+/* Replay the plan's graph on `stream` (asynchronous).  Runs on one stream at a time. */
 vc_status vc_batch_plan_run(vc_batch_plan* plan, hipStream_t stream);
 /* Run the same segments as separate kernel launches, one per segment (the baseline
  * the persistent launch is compared with). */
 vc_status vc_batch_plan_run_separate(vc_batch_plan* plan, hipStream_t stream);
+/* Free the plan; no run of it may still be in flight. */
 vc_status vc_batch_plan_destroy(vc_batch_plan* plan);
 
 /* Human-readable name of a status.  Static string, never NULL. */

@@ -48,6 +48,13 @@ vc_status vcx_set_stream_config(int block, int vpt, int nt);
 vc_status vcx_get_stream_config(int* block, int* vpt, int* nt);
 vc_status vcx_load_tuning(const char* path);
 
+/* The plan's segments as separate launches (as vc_batch_plan_run_separate), captured once
+ * into a second HIP graph on first use and replayed: the launch-overhead baseline between
+ * plain separate launches and the persistent kernel. */
+vc_status vcx_batch_plan_run_separate_graph(vc_batch_plan* plan, hipStream_t stream);
+/* Number of tiles the plan's persistent kernel walks and its grid size (workgroups). */
+vc_status vcx_batch_plan_info(const vc_batch_plan* plan, uint64_t* total_tiles, uint32_t* grid);
+
 /* dst[0:bytes) = src[0:bytes): the attainable-bandwidth reference.  16-byte aligned. */
 vc_status vcb_copy(const void* src, void* dst, size_t bytes, hipStream_t stream);
 

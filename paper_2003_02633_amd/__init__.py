@@ -69,6 +69,8 @@ _SIGS = {
     "vcx_set_stream_config": ([C.c_int, C.c_int, C.c_int], C.c_int),
     "vcx_get_stream_config": ([C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
     "vcx_load_tuning": ([C.c_char_p], C.c_int),
+    "vcx_batch_plan_run_separate_graph": ([_vp, _vp], C.c_int),
+    "vcx_batch_plan_info": ([_vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint32)], C.c_int),
 }
 
 
@@ -240,6 +242,14 @@ def get_stream_config():
     return b.value, v.value, t.value
 
 
+def _seg_ptr(seg, key):
+    """device address of a segment operand: a tensor, a raw integer address, or None"""
+    v = seg.get(key)
+    if v is None:
+        return None
+    return int(v) if isinstance(v, int) else v.data_ptr()
+
+
 class BatchPlan:
     """Persistent batched launch over a segment table (see vc_batch_plan_create)."""
 
@@ -247,8 +257,8 @@ class BatchPlan:
         arr = (vc_segment * len(segments))()
         for i, s in enumerate(segments):
             arr[i] = vc_segment(OPS[s["op"]], float(s.get("alpha", 1.0)), int(s["n"]),
-                                s["a"].data_ptr(), s["b"].data_ptr() if s.get("b") is not None else None,
-                                s["out"].data_ptr())
+                                _seg_ptr(s, "a"), _seg_ptr(s, "b"),
+                                _seg_ptr(s, "out"))
         self._keep = segments
         self._c = c
         self.plan = C.c_void_p()
@@ -260,6 +270,16 @@ class BatchPlan:
 
     def run_separate(self, stream=None):
         _check(lib().vc_batch_plan_run_separate(self.plan, _stream(stream)), "vc_batch_plan_run_separate")
+
+    def run_separate_graph(self, stream=None):
+        _check(lib().vcx_batch_plan_run_separate_graph(self.plan, _stream(stream)),
+               "vcx_batch_plan_run_separate_graph")
+
+    def info(self):
+        """(tiles walked by the persistent kernel, its grid size)"""
+        t, g = C.c_uint64(), C.c_uint32()
+        _check(lib().vcx_batch_plan_info(self.plan, C.byref(t), C.byref(g)), "vcx_batch_plan_info")
+        return t.value, g.value
 
     def close(self):
         if self.plan:

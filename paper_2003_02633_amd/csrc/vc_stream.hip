@@ -331,37 +331,6 @@ static vc_status norm2_t(const uint64_t* a, size_t n, float* parts, int np, floa
   return launch_status();
 }
 
-// layout x mode x precision dispatch (decode-only paths ignore the precision)
-#define VC_CASES(FN, PR, ...)                                                             \
-  case 0: return FN<L0722, PLAIN, PR>(__VA_ARGS__);                                       \
-  case 1: return FN<L0722, TANH, PR>(__VA_ARGS__);                                        \
-  case 2: return FN<L0722, COS, PR>(__VA_ARGS__);                                         \
-  case 3: return FN<L0722, FRAC, PR>(__VA_ARGS__);                                        \
-  case 4: return FN<L0723, PLAIN, PR>(__VA_ARGS__);                                       \
-  case 8: return FN<L0823, PLAIN, PR>(__VA_ARGS__);                                       \
-  case 12: return FN<L1823, PLAIN, PR>(__VA_ARGS__);
-#define VC_DISPATCH(R, FN, ...)                                                           \
-  do {                                                                                    \
-    if ((R).prec == PREC_F64) {                                                           \
-      switch ((R).layout * 4 + (R).mode) {                                                \
-        VC_CASES(FN, PREC_F64, __VA_ARGS__)                                               \
-        default: return VC_ERROR_UNSUPPORTED_CODEC;                                       \
-      }                                                                                   \
-    } else {                                                                              \
-      switch ((R).layout * 4 + (R).mode) {                                                \
-        VC_CASES(FN, PREC_F32, __VA_ARGS__)                                               \
-        default: return VC_ERROR_UNSUPPORTED_CODEC;                                       \
-      }                                                                                   \
-    }                                                                                     \
-  } while (0)
-#define VC_DISPATCH_NOPREC(R, FN, ...)                                                    \
-  do {                                                                                    \
-    switch ((R).layout * 4 + (R).mode) {                                                  \
-      VC_CASES(FN, PREC_F32, __VA_ARGS__)                                                 \
-      default: return VC_ERROR_UNSUPPORTED_CODEC;                                         \
-    }                                                                                     \
-  } while (0)
-
 vc_status launch_axpy(const Resolved& R, float alpha, const uint64_t* a, const uint64_t* b, uint64_t* c,
                       size_t n, float* dump, hipStream_t s)
 {

@@ -95,3 +95,56 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(vc, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="not built"):
         vc.lib()
+
+
+def _seg(op, n, a, b, out, alpha=1.0):
+    return vc.vc_segment(vc.OPS[op], alpha, n, a, b, out)
+
+
+def _create(lib, segs):
+    arr = (vc.vc_segment * len(segs))(*segs)
+    plan = C.c_void_p()
+    st = lib.vc_batch_plan_create(C.byref(plan), C.byref(vc.codec()), arr, len(segs), None)
+    assert not plan.value
+    return st
+
+
+def test_batch_plan_validation_without_device_work(lib):
+    K = 1 << 20
+    # unknown op
+    assert _create(lib, [vc.vc_segment(9, 1.0, 4, 0x10000, 0x20000, 0x30000)]) == 1
+    # NULL operand / output
+    assert _create(lib, [_seg("axpy", 4, None, 0x20000, 0x30000)]) == 1
+    assert _create(lib, [_seg("dot", 0, None, None, None)]) == 1
+    # misaligned
+    assert _create(lib, [_seg("norm2", 4, 0x10004, None, 0x30000)]) == 2
+    assert _create(lib, [_seg("encode", 4, 0x10002, None, 0x30000)]) == 2
+    # in-segment partial overlap
+    assert _create(lib, [_seg("axpy", 16, 0x10000, 0x20000 + K, 0x10008)]) == 7
+    # one segment writes what another reads, or two write the same memory
+    assert _create(lib, [_seg("axpy", 16, 0x10000, 0x20000, 0x30000),
+                         _seg("norm2", 16, 0x30000 + 64, None, 0x40000)]) == 7
+    assert _create(lib, [_seg("encode", 16, 0x10000, None, 0x30000),
+                         _seg("dot", 16, 0x50000, 0x60000, 0x30000 + 120)]) == 7
+    # nseg bounds and plan pointer
+    arr = (vc.vc_segment * 1)(_seg("norm2", 4, 0x10000, None, 0x30000))
+    plan = C.c_void_p()
+    assert lib.vc_batch_plan_create(C.byref(plan), C.byref(vc.codec()), arr, -1, None) == 1
+    assert lib.vc_batch_plan_create(None, C.byref(vc.codec()), arr, 1, None) == 1
+    assert lib.vc_batch_plan_run(None, None) == 1
+    assert lib.vc_batch_plan_destroy(None) == 0
+
+
+def test_apply_validation_without_device_work(lib):
+    P = C.byref(vc.codec())
+    f = _fake
+    assert lib.vc_fused_apply(P, f(0x10000), 0, 4, f(0x20000), f(0x30000), 8, None) == 1
+    assert lib.vc_fused_apply(P, f(0x10000), 257, 4, f(0x20000), f(0x30000), 8, None) == 1
+    assert lib.vc_fused_apply(P, f(0x10000), 16, 0, f(0x20000), f(0x30000), 8, None) == 1
+    # operator too large for LDS staging: 4*ceil(200/4)*160 floats
+    assert lib.vc_fused_apply(P, f(0x10000), 160, 200, f(0x20000), f(0x30000), 8, None) == 1
+    assert lib.vc_fused_apply(P, f(0x10000), 150, 125, None, f(0x30000), 8, None) == 1
+    assert lib.vc_fused_apply(P, f(0x10000), 150, 125, f(0x20004), f(0x30000), 8, None) == 2
+    assert lib.vc_fused_apply(P, None, 150, 125, None, None, 0, None) == 0
+    bad = vc.codec(mode="tanh")
+    assert lib.vc_fused_apply(C.byref(bad), f(0x10000), 16, 4, f(0x20000), f(0x30000), 8, None) == 3

@@ -1,0 +1,205 @@
+"""GPU parity of the batched persistent launch (vc_batch_plan_*) over a segment table.
+
+Contract:
+  * axpy / encode segments: codes bit-identical to the single-call entry points (vc_axpy,
+    vc_encode) on the same operands -- the persistent kernel runs the same per-vector codec;
+    those entry points are held to the oracle by test_gpu_parity;
+  * dot / norm2 segments: within 4e-6 of sum |a||b| (resp. sum |a|^2) of the FP64 oracle;
+    deterministic (two replays agree bit for bit); an empty segment gives exactly 0;
+  * graph replays: every replay, with eager work in between, rewrites the same results;
+  * the separate-launch paths (plain and graph-captured) agree with each other bit for bit.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2003_02633_amd as vc
+from paper_2003_02633_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+ALPHA = float(np.float32(0.7))
+
+
+def say(m):
+    print(m, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU test without a GPU"
+    vc.lib()
+    return torch
+
+
+def up(torch, arr, pad=0):
+    """device copy of arr; with pad > 0 the data starts `pad` elements into the allocation
+    (breaks 16-byte alignment and exercises the scalar path)"""
+    arr = np.ascontiguousarray(arr)
+    if arr.dtype == np.uint64:
+        arr = arr.view(np.int64)
+    t = torch.from_numpy(arr.reshape(-1)).to("cuda")
+    if pad:
+        big = torch.empty(t.numel() + pad, dtype=t.dtype, device="cuda")
+        big[pad:] = t
+        t = big[pad:]
+    return t
+
+
+def build_segments(torch, co, lengths, ops, pad_every=0):
+    """device segments plus host copies of their operands"""
+    segs, host = [], []
+    for i, (n, op) in enumerate(zip(lengths, ops)):
+        n = int(n)
+        pad = 1 if (pad_every and i % pad_every == pad_every - 1) else 0
+        if op == "encode":
+            x = inputs.gaussian_with_edges(n - 11, 100 + i) if n >= 11 else inputs.gaussian(n, 100 + i)
+            ta = up(torch, x, 3 * pad)
+            out = torch.empty(max(n, 1), dtype=torch.int64, device="cuda")
+            segs.append({"op": op, "n": n, "a": ta, "out": out})
+            host.append({"x": x})
+            continue
+        wa = O.encode(co, inputs.gaussian(n, 200 + i))
+        wb = O.encode(co, inputs.gaussian(n, 300 + i)) if op in ("axpy", "dot") else None
+        ta = up(torch, wa, pad) if n else torch.empty(1, dtype=torch.int64, device="cuda")
+        tb = (up(torch, wb, pad) if n else torch.empty(1, dtype=torch.int64, device="cuda")) \
+            if wb is not None else None
+        if op == "axpy":
+            out = torch.empty(max(n, 1), dtype=torch.int64, device="cuda")
+        else:
+            out = torch.full((1,), float("nan"), dtype=torch.float32, device="cuda")
+        segs.append({"op": op, "n": n, "a": ta, "b": tb, "out": out, "alpha": ALPHA})
+        host.append({"wa": wa, "wb": wb})
+    return segs, host
+
+
+def expected_codes(torch, c, segs):
+    """per axpy/encode segment: the single-call entry point's result"""
+    exp = {}
+    for i, s in enumerate(segs):
+        if s["n"] == 0:
+            continue
+        if s["op"] == "axpy":
+            exp[i] = vc.vc_axpy(c, ALPHA, s["a"], s["b"]).cpu()
+        elif s["op"] == "encode":
+            exp[i] = vc.vc_encode(c, s["a"].view(-1, 3)).cpu()
+    torch.cuda.synchronize()
+    return exp
+
+
+def check_results(torch, co, segs, host, exp, label):
+    torch.cuda.synchronize()
+    red = {}
+    for i, s in enumerate(segs):
+        n = s["n"]
+        if s["op"] in ("axpy", "encode"):
+            if n == 0:
+                continue
+            got = s["out"][:n].cpu()
+            assert torch.equal(got, exp[i]), f"{label}: segment {i} ({s['op']}, n={n}) differs"
+        else:
+            v = float(s["out"].cpu()[0])
+            red[i] = v
+            if n == 0:
+                assert v == 0.0, f"{label}: empty {s['op']} segment {i} gave {v}"
+                continue
+            if s["op"] == "dot":
+                ref = O.dot(co, host[i]["wa"], host[i]["wb"])
+                A, B = O.decode64(co, host[i]["wa"]), O.decode64(co, host[i]["wb"])
+                scale = float((np.linalg.norm(A, axis=1) * np.linalg.norm(B, axis=1)).sum())
+            else:
+                ref = O.norm2(co, host[i]["wa"])
+                scale = ref
+            assert abs(v - ref) <= 4e-6 * scale, f"{label}: {s['op']} segment {i} n={n}: {v} vs {ref}"
+    return red
+
+
+def clobber(torch, segs):
+    for s in segs:
+        if s["op"] in ("axpy", "encode"):
+            s["out"].fill_(-1)
+        else:
+            s["out"].fill_(float("nan"))
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_batch_mixed_segments(torch_dev, precision):
+    torch = torch_dev
+    lengths, ops = inputs.segments(nseg=64, seed=3, lo_exp=3.0, hi_exp=5.0)
+    # edge segments: empty of every op, single vectors, one tile +- 1, unaligned operands
+    lengths = list(lengths) + [0, 0, 0, 0, 1, 1, 1, 1, 511, 512, 513, 1025]
+    ops = list(ops) + ["axpy", "dot", "norm2", "encode", "axpy", "dot", "norm2", "encode",
+                       "axpy", "dot", "norm2", "encode"]
+    say(f"case: batch precision={precision} nseg={len(lengths)} total={int(np.sum(lengths))}")
+    c, co = vc.codec(precision=precision), O.codec()
+    segs, host = build_segments(torch, co, lengths, ops, pad_every=5)
+    exp = expected_codes(torch, c, segs)
+    plan = vc.BatchPlan(c, segs)
+    tiles, grid = plan.info()
+    say(f"plan: {tiles} tiles, grid {grid}")
+    assert tiles == sum((int(n) + 511) // 512 for n in lengths)
+
+    clobber(torch, segs)
+    plan.run()
+    first = check_results(torch, co, segs, host, exp, "persistent")
+    for rep in range(3):
+        clobber(torch, segs)
+        scratch = vc.vc_norm2(c, segs[-2]["a"])   # eager library work between replays
+        torch.cuda.synchronize()
+        del scratch
+        plan.run()
+        again = check_results(torch, co, segs, host, exp, f"replay {rep}")
+        assert again == first, "reductions not deterministic across replays"
+
+    clobber(torch, segs)
+    plan.run_separate()
+    sep = check_results(torch, co, segs, host, exp, "separate")
+    for rep in range(2):
+        clobber(torch, segs)
+        plan.run_separate_graph()
+        sep_g = check_results(torch, co, segs, host, exp, f"separate graph {rep}")
+        assert sep_g == sep
+    plan.close()
+
+
+def test_batch_in_place_axpy(torch_dev):
+    torch = torch_dev
+    say("case: batch in-place axpy")
+    c, co = vc.codec(), O.codec()
+    n = 5000
+    wa = O.encode(co, inputs.gaussian(n, 41))
+    wb = O.encode(co, inputs.gaussian(n, 42))
+    ta, tb = up(torch, wa), up(torch, wb)
+    ref = vc.vc_axpy(c, ALPHA, ta, tb).cpu()
+    plan = vc.BatchPlan(c, [{"op": "axpy", "n": n, "a": ta, "b": tb, "out": ta, "alpha": ALPHA}])
+    plan.run()
+    torch.cuda.synchronize()
+    assert torch.equal(ta.cpu(), ref)
+    plan.close()
+
+
+def test_batch_variant_codec(torch_dev):
+    """fractional split codec through the persistent kernel"""
+    torch = torch_dev
+    say("case: batch frac P=163840")
+    c, co = vc.codec(mode="frac", P=163840), O.codec(mode="frac", P=163840)
+    lengths, ops = [3000, 7001, 20000, 1], ["axpy", "encode", "dot", "norm2"]
+    segs, host = build_segments(torch, co, lengths, ops)
+    exp = expected_codes(torch, c, segs)
+    plan = vc.BatchPlan(c, segs)
+    plan.run()
+    check_results(torch, co, segs, host, exp, "frac")
+    plan.close()
+
+
+def test_batch_empty_plan(torch_dev):
+    plan = vc.BatchPlan(vc.codec(), [])
+    plan.run()
+    plan.run_separate()
+    plan.run_separate_graph()
+    assert plan.info() == (0, 1)
+    plan.close()
