@@ -209,8 +209,8 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (--gpus {args.gpus} requested); "
-              "the method is data-parallel over independent vectors and its multi-GPU sharding is "
-              "described in DESIGN.md, but no multi-GPU path is built.", file=sys.stderr)
+              "the method is data-parallel over independent vectors (each GPU would take a contiguous "
+              "range), but no multi-GPU path is built.", file=sys.stderr)
         sys.exit(2)
 
     import torch

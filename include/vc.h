@@ -71,7 +71,8 @@ enum { VC_COMPAND_PHI = 1, VC_COMPAND_THETA = 2 };
  * (the paper's implementation section prescribes it for phi; full-rate FMA on MI355X), or
  * single precision only, with double-float error-free transformations.  Both produce the
  * same codes up to the one-ulp window; decode and all post-decode arithmetic are single
- * precision in both. */
+ * precision in both.  The companding modes (tanh, cosine) need VC_PREC_F64; with VC_PREC_F32
+ * every entry point returns VC_ERROR_UNSUPPORTED_CODEC for them. */
 typedef enum { VC_PREC_F64 = 0, VC_PREC_F32 = 1 } vc_precision;
 
 /* Codec description.  Plain data, owned by the caller; build it with vc_codec_init

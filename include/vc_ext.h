@@ -39,13 +39,15 @@ vc_status vcb_axpy_f16x4(float alpha, const uint16_t* a, const uint16_t* b, uint
                          hipStream_t stream);
 
 /* Launch configuration of the streaming compressed axpy (default layout, uniform
- * quantisation): threads per block (128, 256, 512), vectors per thread and grid step
- * (2 or 4), non-temporal loads/stores (0/1).  Process-wide; not thread-safe with
- * concurrent launches.  Unsupported combinations return VC_ERROR_UNSUPPORTED_CODEC.
- * vcx_load_tuning reads "axpy block=B vpt=V nt=T" lines from a text file (the cache the
- * autotuner writes); the library applies the file named by $VC_TUNE_CACHE on first use. */
-vc_status vcx_set_stream_config(int block, int vpt, int nt);
-vc_status vcx_get_stream_config(int* block, int* vpt, int* nt);
+ * quantisation) for one encoder precision (VC_PREC_F64 or VC_PREC_F32; -1 sets both):
+ * threads per block (128, 256, 512), vectors per thread and grid step (2 or 4),
+ * non-temporal loads/stores (0/1).  Process-wide; not thread-safe with concurrent
+ * launches.  Unsupported combinations return VC_ERROR_UNSUPPORTED_CODEC and change nothing.
+ * vcx_load_tuning reads lines "axpy f64 block=B vpt=V nt=T" (or f32, or no precision for
+ * both) from a text file, the cache the autotuner writes; the library applies the file
+ * named by $VC_TUNE_CACHE on the first vc_axpy call. */
+vc_status vcx_set_stream_config(int precision, int block, int vpt, int nt);
+vc_status vcx_get_stream_config(int precision, int* block, int* vpt, int* nt);
 vc_status vcx_load_tuning(const char* path);
 
 /* The plan's segments as separate launches (as vc_batch_plan_run_separate), captured once

@@ -12,8 +12,8 @@
  *   - fractional splitting n_p = n_phi (n_theta_max + 1) + n_theta    §2.4, Eq. (q_split)
  *   - tanh and cosine companding maps                                 §2.5
  *
- * Readings of points where the paper is silent or ambiguous (all listed in
- * DESIGN.md) are marked "reading:" below.
+ * Readings of points where the paper is silent or ambiguous are marked
+ * "reading:" below.
  *
  * Arithmetic is FP64 and integer.  The only places where FP64 rounding could
  * change an integer decision are (a) the magnitude, which the paper defines as

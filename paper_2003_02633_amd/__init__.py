@@ -66,8 +66,8 @@ _SIGS = {
     "vcb_axpy_bf16x4": ([C.c_float, _vp, _vp, _vp, C.c_size_t, _vp], C.c_int),
     "vcb_axpy_f16x4": ([C.c_float, _vp, _vp, _vp, C.c_size_t, _vp], C.c_int),
     "vcb_copy": ([_vp, _vp, C.c_size_t, _vp], C.c_int),
-    "vcx_set_stream_config": ([C.c_int, C.c_int, C.c_int], C.c_int),
-    "vcx_get_stream_config": ([C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
+    "vcx_set_stream_config": ([C.c_int, C.c_int, C.c_int, C.c_int], C.c_int),
+    "vcx_get_stream_config": ([C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
     "vcx_load_tuning": ([C.c_char_p], C.c_int),
     "vcx_batch_plan_run_separate_graph": ([_vp, _vp], C.c_int),
     "vcx_batch_plan_info": ([_vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint32)], C.c_int),
@@ -232,13 +232,16 @@ def vcb_copy(src, dst, stream=None):
     return dst
 
 
-def set_stream_config(block: int, vpt: int, nt: int):
-    _check(lib().vcx_set_stream_config(block, vpt, nt), "vcx_set_stream_config")
+def set_stream_config(block: int, vpt: int, nt: int, precision: str = "both"):
+    """axpy launch configuration for one encoder precision ("f64", "f32") or both"""
+    p = -1 if precision == "both" else PRECISIONS[precision]
+    _check(lib().vcx_set_stream_config(p, block, vpt, nt), "vcx_set_stream_config")
 
 
-def get_stream_config():
+def get_stream_config(precision: str = "f64"):
     b, v, t = C.c_int(), C.c_int(), C.c_int()
-    _check(lib().vcx_get_stream_config(C.byref(b), C.byref(v), C.byref(t)), "vcx_get_stream_config")
+    _check(lib().vcx_get_stream_config(PRECISIONS[precision], C.byref(b), C.byref(v), C.byref(t)),
+           "vcx_get_stream_config")
     return b.value, v.value, t.value
 
 

@@ -85,16 +85,26 @@ static vc_status axpy_common(const vc_codec* c, float alpha, const uint64_t* a, 
   return launch_axpy(R, alpha, a, b, out, n, dump, stream);
 }
 
-vc_status vcx_set_stream_config(int block, int vpt, int nt)
+// public precision (vc_precision) -> device Prec index; -1 = both
+static int prec_index(int precision)
 {
-  if (vpt != 2 && vpt != 4) return VC_ERROR_UNSUPPORTED_CODEC;
-  return set_axpy_cfg(block, vpt / 2, nt);
+  if (precision < 0) return -1;
+  return precision == VC_PREC_F64 ? PREC_F64 : precision == VC_PREC_F32 ? PREC_F32 : -2;
 }
 
-vc_status vcx_get_stream_config(int* block, int* vpt, int* nt)
+vc_status vcx_set_stream_config(int precision, int block, int vpt, int nt)
+{
+  const int p = prec_index(precision);
+  if (p < -1 || (vpt != 2 && vpt != 4)) return VC_ERROR_UNSUPPORTED_CODEC;
+  return set_axpy_cfg(p, block, vpt / 2, nt);
+}
+
+vc_status vcx_get_stream_config(int precision, int* block, int* vpt, int* nt)
 {
   if (!block || !vpt || !nt) return VC_ERROR_INVALID_VALUE;
-  const StreamCfg g = stream_cfg(0, 0);
+  const int p = prec_index(precision);
+  if (p < 0) return VC_ERROR_UNSUPPORTED_CODEC;
+  const StreamCfg g = stream_cfg(p);
   *block = g.block;
   *vpt = 2 * g.vpt;
   *nt = g.nt;
@@ -108,9 +118,15 @@ vc_status vcx_load_tuning(const char* path)
   if (!f) return VC_ERROR_INVALID_VALUE;
   char line[256];
   vc_status st = VC_SUCCESS;
-  while (fgets(line, sizeof line, f)) {
+  while (fgets(line, sizeof line, f) && st == VC_SUCCESS) {
     int b = 0, v = 0, t = 0;
-    if (sscanf(line, "axpy block=%d vpt=%d nt=%d", &b, &v, &t) == 3) st = set_axpy_cfg(b, v / 2, t);
+    char prec[8] = {0};
+    if (sscanf(line, "axpy %7s block=%d vpt=%d nt=%d", prec, &b, &v, &t) == 4) {
+      const int p = strcmp(prec, "f64") == 0 ? VC_PREC_F64 : strcmp(prec, "f32") == 0 ? VC_PREC_F32 : -2;
+      st = p == -2 ? VC_ERROR_INVALID_VALUE : vcx_set_stream_config(p, b, v, t);
+    } else if (sscanf(line, "axpy block=%d vpt=%d nt=%d", &b, &v, &t) == 3) {
+      st = vcx_set_stream_config(-1, b, v, t);
+    }
   }
   fclose(f);
   return st;

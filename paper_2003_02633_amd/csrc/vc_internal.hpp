@@ -17,8 +17,8 @@ struct StreamCfg {
   int vpt;         // vectors per thread and grid step (2 or 4)
   int nt;          // non-temporal loads/stores
 };
-StreamCfg stream_cfg(int op, size_t n);
-vc_status set_axpy_cfg(int block, int vpt, int nt);
+StreamCfg stream_cfg(int prec);                                   // prec: PREC_F32 / PREC_F64
+vc_status set_axpy_cfg(int prec, int block, int vpt, int nt);     // prec -1: both
 
 vc_status launch_encode(const Resolved& R, const float* xyz, uint64_t* codes, size_t n, hipStream_t s);
 vc_status launch_decode(const Resolved& R, const uint64_t* codes, float* xyz, size_t n, hipStream_t s);

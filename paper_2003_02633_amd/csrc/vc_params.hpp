@@ -166,6 +166,10 @@ inline vc_status resolve(const vc_codec* c, Resolved* R)
   if (c->mag_round != VC_MAG_RNE) return VC_ERROR_UNSUPPORTED_CODEC;   // truncation: oracle-only
   if (c->precision > VC_PREC_F32 || c->reserved0 != 0) return VC_ERROR_INVALID_VALUE;
   if (c->mode != VC_MODE_PLAIN && c->layout != VC_LAYOUT_0_7_22_17_18) return VC_ERROR_UNSUPPORTED_CODEC;
+  // the single-precision encoder's companded level near the phi poles cancels to ~2^-24 of
+  // the level count, far outside the one-ulp window; companding needs the FP64 encoder
+  if (c->precision == VC_PREC_F32 && (c->mode == VC_MODE_TANH || c->mode == VC_MODE_COS))
+    return VC_ERROR_UNSUPPORTED_CODEC;
   memset(R, 0, sizeof(*R));
   R->layout = (int)c->layout;
   R->mode = (int)c->mode;

@@ -210,21 +210,19 @@ static inline unsigned grid_for(size_t work, size_t per_block, unsigned cap)
   return (unsigned)g;
 }
 
-// ---- launch configuration of the streaming axpy (set by the autotuner, see vcx_set_stream_config)
-static StreamCfg g_axpy_cfg = {256, 1, 1};
+// ---- launch configuration of the streaming axpy per encoder precision (indexed by Prec), set by
+// the autotuner; defaults are the fastest configurations measured at N = 2^27 on MI355X
+static StreamCfg g_axpy_cfg[2] = {{512, 1, 1} /* PREC_F32 */, {512, 2, 1} /* PREC_F64 */};
 
-StreamCfg stream_cfg(int op, size_t)
-{
-  (void)op;
-  return g_axpy_cfg;
-}
+StreamCfg stream_cfg(int prec) { return g_axpy_cfg[prec == PREC_F64 ? 1 : 0]; }
 
-vc_status set_axpy_cfg(int block, int vpt, int nt)
+vc_status set_axpy_cfg(int prec, int block, int vpt, int nt)
 {
   const bool okb = block == 128 || block == 256 || block == 512;
   const bool oku = vpt == 1 || vpt == 2;   // grid steps of 2 codes per lane
-  if (!okb || !oku || (nt != 0 && nt != 1)) return VC_ERROR_UNSUPPORTED_CODEC;
-  g_axpy_cfg = {block, vpt, nt};
+  if (!okb || !oku || (nt != 0 && nt != 1) || prec < -1 || prec > 1) return VC_ERROR_UNSUPPORTED_CODEC;
+  for (int p = 0; p < 2; p++)
+    if (prec < 0 || prec == p) g_axpy_cfg[p] = {block, vpt, nt};
   return VC_SUCCESS;
 }
 
@@ -251,7 +249,7 @@ static vc_status axpy_t(const Resolved& R, float alpha, const uint64_t* a, const
 {
   // tuned variants for the default layout and uniform quantisation; other codecs use 256 x 1, NT
   if constexpr (std::is_same<L, L0722>::value && MODE == PLAIN) {
-    const StreamCfg g = g_axpy_cfg;
+    const StreamCfg g = g_axpy_cfg[PREC == PREC_F64 ? 1 : 0];
     const int key = (g.block == 128 ? 0 : g.block == 256 ? 1 : 2) * 4 + (g.vpt == 2 ? 2 : 0) + g.nt;
     switch (key) {
       case 0: return axpy_launch<L, MODE, PREC, 128, 1, false>(R, alpha, a, b, c, n, dump, s);

@@ -8,8 +8,8 @@ All draws use numpy's PCG64 in FP64 and round to FP32 at the end.  Large draws
 are produced in fixed-size chunks from one generator, so a given (seed, n)
 always yields the same array.
 
-Workloads (shapes and distributions follow the paper's test settings and the
-benchmark configurations stated in the design doc):
+Workloads (shapes and distributions follow the paper's test settings: the unit ball of
+§2.2/§3, the streaming kernel of §5 and the flux-reconstruction fields of §4):
   * ``gaussian_with_edges``  -- N(0,1) components plus axis/zero/extreme cases
   * ``sphere_loguniform``    -- directions uniform on S^2, |x| log-uniform
   * ``unit_sphere`` / ``unit_cube`` -- the unit-ball samplers of §2.2 and §3

@@ -4,7 +4,7 @@ Sweeps every launch configuration the library is built with on a workload of N v
 (default 2^27, the benchmark size), checks that all configurations produce bit-identical
 codes, and writes the fastest one as a tuning cache:
 
-    axpy block=<B> vpt=<V> nt=<T>
+    axpy <f64|f32> block=<B> vpt=<V> nt=<T>
 
 The library applies the file named by $VC_TUNE_CACHE on first use, and
 ``vcx_load_tuning(path)`` applies any cache explicitly.
@@ -34,10 +34,10 @@ def sweep(n: int = 1 << 27, precision: str = "f64", steps: int = 10, warmup: int
     out = torch.empty_like(a)
     ref = None
     results = []
-    saved = vc.get_stream_config()
+    saved = vc.get_stream_config(precision)
     try:
         for (blk, vpt, nt) in CONFIGS:
-            vc.set_stream_config(blk, vpt, nt)
+            vc.set_stream_config(blk, vpt, nt, precision)
             for _ in range(warmup):
                 vc.vc_axpy(c, 0.7, a, b, out)
             torch.cuda.synchronize()
@@ -55,7 +55,7 @@ def sweep(n: int = 1 << 27, precision: str = "f64", steps: int = 10, warmup: int
             results.append({"block": blk, "vpt": vpt, "nt": nt, "ms": ms, "gvecs": n / ms / 1e6, "identical": same})
             log(f"[tune] block={blk} vpt={vpt} nt={nt}: {ms:.4f} ms  {n / ms / 1e6:.1f} Gvec/s  identical={same}")
     finally:
-        vc.set_stream_config(*saved)
+        vc.set_stream_config(*saved, precision)
     if not all(r["identical"] for r in results):
         raise RuntimeError("launch configurations disagree")
     return results
@@ -74,7 +74,7 @@ def main():
     with open(args.out, "w") as f:
         f.write(f"# compressed axpy launch configuration, N={args.n}, encoder {args.precision}, "
                 f"{best['gvecs']:.1f} Gvec/s\n")
-        f.write(f"axpy block={best['block']} vpt={best['vpt']} nt={best['nt']}\n")
+        f.write(f"axpy {args.precision} block={best['block']} vpt={best['vpt']} nt={best['nt']}\n")
     if args.json:
         with open(args.json, "w") as f:
             json.dump({"n": args.n, "precision": args.precision, "results": res, "best": best}, f, indent=1)

@@ -81,6 +81,10 @@ def test_validation_errors_without_device_work(lib):
     assert lib.vc_encode(C.byref(bad), _fake(0x10000), _fake(0x20000), n, None) == 1
     bad = vc.codec(mode="tanh", gamma=5.0)
     assert lib.vc_encode(C.byref(bad), _fake(0x10000), _fake(0x20000), n, None) == 3
+    bad = vc.codec(mode="tanh", precision="f32")
+    assert lib.vc_encode(C.byref(bad), _fake(0x10000), _fake(0x20000), n, None) == 3
+    bad = vc.codec(mode="cos", precision="f32")
+    assert lib.vc_axpy(C.byref(bad), 1.0, _fake(0x10000), _fake(0x20000), _fake(0x30000), n, None) == 3
     bad = vc.codec("0,8,23-16-17", mode="tanh")
     assert lib.vc_encode(C.byref(bad), _fake(0x10000), _fake(0x20000), n, None) == 3
     # reductions need an output
@@ -148,3 +152,25 @@ def test_apply_validation_without_device_work(lib):
     assert lib.vc_fused_apply(P, None, 150, 125, None, None, 0, None) == 0
     bad = vc.codec(mode="tanh")
     assert lib.vc_fused_apply(C.byref(bad), f(0x10000), 16, 4, f(0x20000), f(0x30000), 8, None) == 3
+
+
+def test_tuning_cache_parsing(lib, tmp_path):
+    saved = {p: vc.get_stream_config(p) for p in ("f64", "f32")}
+    try:
+        f = tmp_path / "tune.txt"
+        f.write_text("# comment\naxpy f64 block=256 vpt=2 nt=0\n")
+        assert lib.vcx_load_tuning(str(f).encode()) == 0
+        assert vc.get_stream_config("f64") == (256, 2, 0)
+        assert vc.get_stream_config("f32") == saved["f32"]
+        f.write_text("axpy block=128 vpt=4 nt=1\n")
+        assert lib.vcx_load_tuning(str(f).encode()) == 0
+        assert vc.get_stream_config("f64") == vc.get_stream_config("f32") == (128, 4, 1)
+        f.write_text("axpy f16 block=128 vpt=4 nt=1\n")
+        assert lib.vcx_load_tuning(str(f).encode()) == 1
+        assert lib.vcx_set_stream_config(-1, 100, 2, 1) == 3
+        assert lib.vcx_set_stream_config(-1, 256, 3, 1) == 3
+        assert lib.vcx_load_tuning(str(tmp_path / "missing").encode()) == 1
+    finally:
+        for p, (b, v, t) in saved.items():
+            vc.set_stream_config(b, v, t, p)
+    assert vc.get_stream_config("f64") == saved["f64"]
