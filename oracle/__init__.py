@@ -92,6 +92,7 @@ def lib():
         L.vco_norm2.restype = C.c_double
         L.vco_apply.argtypes = [cp, vp, C.c_int, C.c_int, vp, vp, C.c_size_t, C.c_int]
         L.vco_max_threads.restype = C.c_int
+        L.vco_error_hist.argtypes = [cp, vp, C.c_size_t, vp, C.c_int, vp, vp, C.c_int]
         _lib = L
     return _lib
 
@@ -218,6 +219,28 @@ def apply(c: Codec, M, U, threads: int = 0) -> np.ndarray:
     lib().vco_apply(C.byref(c), M.ctypes.data, rows, cols, U.ctypes.data, out.ctypes.data,
                     U.shape[0], threads)
     return out
+
+
+def log_edges(lo_exp: float = -12.0, hi_exp: float = -2.0, per_decade: int = 10) -> np.ndarray:
+    """histogram edges 10^(lo + i / per_decade), i = 0 .. (hi - lo) per_decade, in FP64"""
+    k = int(round((hi_exp - lo_exp) * per_decade))
+    return 10.0 ** (lo_exp + np.arange(k + 1, dtype=np.float64) / per_decade)
+
+
+ERROR_KINDS = ("vector", "angle", "magnitude")
+
+
+def error_hist(c: Codec, xyz, edges, threads: int = 0):
+    """(counts [3, nedges+1], excluded, stats [3, 3] = (sum, sum of squares, max)) of the codec's
+    errors over xyz (see vco_error_hist)."""
+    a = _f32xyz(xyz)
+    edges = np.ascontiguousarray(edges, dtype=np.float64)
+    ne = edges.shape[0]
+    counts = np.zeros(3 * (ne + 1) + 1, dtype=np.uint64)
+    stats = np.zeros(9, dtype=np.float64)
+    lib().vco_error_hist(C.byref(c), a.ctypes.data, a.shape[0], edges.ctypes.data, ne, counts.ctypes.data,
+                         stats.ctypes.data, threads)
+    return counts[:-1].reshape(3, ne + 1), int(counts[-1]), stats.reshape(3, 3)
 
 
 def rn32_fma(alpha: float, a: float, b: float) -> float:

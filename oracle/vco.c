@@ -24,6 +24,7 @@
 #include "vco.h"
 #include <math.h>
 #include <float.h>
+#include <stdlib.h>
 #include <string.h>
 #ifdef _OPENMP
 #include <omp.h>
@@ -567,4 +568,88 @@ void vco_apply(const vco_codec* c, const float* M, int rows, int cols, const uin
       }
     }
   }
+}
+
+/* ------------------------------------------------------------------------- */
+/* error statistics of the codec (the error measures of §2.2-§2.3)            */
+/* ------------------------------------------------------------------------- */
+
+/* magnitude r_hat of a regular code from its fields (§2.3); 0 for the zero code,
+ * -1 for the reserved code */
+static double code_magnitude(const vco_codec* c, uint64_t w)
+{
+  const uint64_t E = (w >> (c->m + c->p + c->t)) & mask_bits(c->e);
+  const uint64_t M = (w >> (c->p + c->t)) & mask_bits(c->m);
+  if (E == mask_bits(c->e)) return -1.0;
+  if (E == 0) return keeps_subnormals(c) ? (double)M * ldexp(1.0, 1 - c->bias - c->m) : 0.0;
+  return ldexp(1.0 + ldexp((double)M, -c->m), (int)E - c->bias);
+}
+
+static int bin_of(double e, const double* edges, int nedges)
+{
+  int k = 0;
+  while (k < nedges && edges[k] <= e) k++;
+  return k;
+}
+
+void vco_error_hist(const vco_codec* c, const float* xyz, size_t n, const double* edges, int nedges,
+                    uint64_t* counts, double* stats, int nthreads)
+{
+  const int nb = nedges + 1;
+  const int T = nthr(nthreads);
+  uint64_t* loc = (uint64_t*)calloc((size_t)T * (3 * nb + 1), sizeof(uint64_t));
+  double* ls = (double*)calloc((size_t)T * 9, sizeof(double));
+  long long N = (long long)n;
+#pragma omp parallel num_threads(T)
+  {
+    int tid = 0;
+#ifdef _OPENMP
+    tid = omp_get_thread_num();
+#endif
+    uint64_t* h = loc + (size_t)tid * (3 * nb + 1);
+    double* s = ls + (size_t)tid * 9;
+#pragma omp for schedule(static)
+    for (long long i = 0; i < N; i++) {
+      const float x = xyz[3 * i], y = xyz[3 * i + 1], z = xyz[3 * i + 2];
+      if (!isfinite(x) || !isfinite(y) || !isfinite(z) || (x == 0.0f && y == 0.0f && z == 0.0f)) {
+        h[3 * nb]++;
+        continue;
+      }
+      vco_detail d;
+      const uint64_t w = vco_encode_detail(c, x, y, z, &d);
+      const double rh = code_magnitude(c, w);
+      if (d.saturated || d.flushed || rh <= 0.0) {
+        h[3 * nb]++;
+        continue;
+      }
+      double xh[3];
+      vco_decode64(c, w, xh);
+      const double X = x, Y = y, Z = z;
+      const double r = sqrt(X * X + Y * Y + Z * Z);
+      const double dx = xh[0] - X, dy = xh[1] - Y, dz = xh[2] - Z;
+      const double cx = Y * xh[2] - Z * xh[1], cy = Z * xh[0] - X * xh[2], cz = X * xh[1] - Y * xh[0];
+      double e[3];
+      e[0] = sqrt(dx * dx + dy * dy + dz * dz) / r;                                   /* |x_hat - x| / |x| */
+      e[1] = atan2(sqrt(cx * cx + cy * cy + cz * cz), X * xh[0] + Y * xh[1] + Z * xh[2]); /* angle */
+      e[2] = fabs(rh - r) / r;                                                        /* |r_hat - r| / r */
+      for (int k = 0; k < 3; k++) {
+        h[k * nb + bin_of(e[k], edges, nedges)]++;
+        s[3 * k] += e[k];
+        s[3 * k + 1] += e[k] * e[k];
+        if (e[k] > s[3 * k + 2]) s[3 * k + 2] = e[k];
+      }
+    }
+  }
+  for (int j = 0; j < 3 * nb + 1; j++) counts[j] = 0;
+  for (int k = 0; k < 9; k++) stats[k] = 0.0;
+  for (int t = 0; t < T; t++) {
+    for (int j = 0; j < 3 * nb + 1; j++) counts[j] += loc[(size_t)t * (3 * nb + 1) + j];
+    for (int k = 0; k < 3; k++) {
+      stats[3 * k] += ls[t * 9 + 3 * k];
+      stats[3 * k + 1] += ls[t * 9 + 3 * k + 1];
+      if (ls[t * 9 + 3 * k + 2] > stats[3 * k + 2]) stats[3 * k + 2] = ls[t * 9 + 3 * k + 2];
+    }
+  }
+  free(loc);
+  free(ls);
 }

@@ -83,6 +83,15 @@ void vco_apply(const vco_codec* c, const float* M, int rows, int cols, const uin
                double* out, size_t n_elem, int nthreads);
 int vco_max_threads(void);
 
+/* Error statistics of encode -> FP64 decode over a batch of vectors (the error measures of
+ * §2.2-§2.3), for each finite non-zero input whose code is neither flushed nor saturated:
+ *   k = 0: |x_hat - x| / |x|,  k = 1: the angle between x and x_hat,  k = 2: |r_hat - |x|| / |x|
+ * (x_hat the FP64 decode, r_hat the code's magnitude).  Histogram bin = number of edges <= e
+ * (edges ascending, 0..nedges): counts[k (nedges+1) + bin]; counts[3 (nedges+1)] = vectors left
+ * out.  stats[3k] = sum e, stats[3k+1] = sum e^2, stats[3k+2] = max e. */
+void vco_error_hist(const vco_codec* c, const float* xyz, size_t n, const double* edges, int nedges,
+                    uint64_t* counts, double* stats, int nthreads);
+
 #ifdef __cplusplus
 }
 #endif

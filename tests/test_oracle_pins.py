@@ -556,3 +556,82 @@ def test_axpy_definition():
     # plus the single-precision rounding of c32 relative to |c|
     scale = (al * np.linalg.norm(O.decode64(c, a), axis=1) + np.linalg.norm(O.decode64(c, b), axis=1))[ok]
     assert (err <= bound + 2 * 2.0 ** -24 * scale / nrm[ok] + 1e-12).all()
+
+
+# ---------------------------------------------------------------- error statistics (histograms)
+def test_error_hist_reproduces_table_cpp_error(paper):
+    """Table (C++_error), double/double row on S^2: mean and max normalised error, from the
+    histogram function's own sums (not from a separate error computation)."""
+    edges = O.log_edges()
+    h, excluded, st = O.error_hist(O.codec(), inputs.unit_sphere(1_000_000, 51), edges)
+    n = int(h[0].sum())
+    assert n == 1_000_000 and excluded == 0
+    assert int(h[1].sum()) == n and int(h[2].sum()) == n
+    mean = st[0, 0] / n
+    sd = math.sqrt(st[0, 1] / n - mean * mean)
+    assert abs(mean - paper["dd_sphere_mean"]) < 4 * sd / math.sqrt(n) + 5e-10
+    assert 0.95 * paper["dd_sphere_max"] < st[0, 2] <= paper["dd_sphere_max"] * 1.02
+
+
+def test_error_hist_bounds():
+    """Eq. (abs_e): |d theta| <= pi/n_theta_max, |d phi| <= pi/(2 n_phi_max), so the angle between
+    x and x_hat is at most sqrt(eps_phi^2 + eps_theta^2); §2.3 with nearest rounding of the
+    1+22-bit significand: |r_hat - r|/r <= 2^-23.  No histogram count may lie beyond them."""
+    edges = O.log_edges()
+    c = O.codec()
+    eps_t, eps_p = math.pi / 262143, math.pi / (2 * 131071)
+    ang_bound = math.hypot(eps_t, eps_p)
+    x = inputs.sphere_loguniform(400_000, 61)
+    h, excluded, st = O.error_hist(c, x, edges)
+    assert st[1, 2] <= ang_bound * (1 + 1e-9)
+    assert st[2, 2] <= 2.0 ** -23
+    top_ang = int(np.searchsorted(edges, ang_bound, side="right"))
+    top_mag = int(np.searchsorted(edges, 2.0 ** -23, side="right"))
+    assert h[1, top_ang + 1:].sum() == 0 and h[2, top_mag + 1:].sum() == 0
+
+
+def test_error_hist_closed_forms():
+    """+x: theta = 0 and phi = pi/2 are exact half-up ties (Eq. a_disc), so theta_hat = pi/262143
+    and phi_hat - pi/2 = pi/262142 exactly; the great circle distance d satisfies
+    cos d = cos(d theta) cos(d phi), |r_hat - r| = 0, |x_hat - x| = 2 sin(d/2).
+    +z: sin(phi_hat) = 0 exactly, so every error is exactly 0 and falls below the first edge."""
+    edges = O.log_edges()
+    c = O.codec()
+    a, b = math.pi / 262143, math.pi / 262142
+    # d^2 = a^2 + b^2 - a^2 b^2 / 3 + O(d^6) from the cosine series; the next term is ~1e-30
+    d = math.sqrt(a * a + b * b - a * a * b * b / 3)
+    h, excluded, st = O.error_hist(c, np.array([[1.0, 0.0, 0.0]], dtype=np.float32), edges)
+    assert excluded == 0
+    assert abs(st[1, 0] - d) <= 1e-9 * d
+    assert abs(st[0, 0] - 2 * math.sin(d / 2)) <= 1e-9 * d
+    assert st[2, 0] == 0.0
+    h, excluded, st = O.error_hist(c, np.array([[0.0, 0.0, 1.0], [0.0, 0.0, -4.0]], dtype=np.float32), edges)
+    assert (st[:, 0] == 0).all() and (h[:, 0] == 2).all()
+
+
+def test_error_hist_exclusions_and_binning():
+    """zero, non-finite, flushed and saturated inputs are left out; bin = number of edges <= e
+    (checked against numpy's searchsorted on an independently binned copy of the sums)."""
+    edges = np.array([1e-9, 1e-7, 3e-6, 1e-5], dtype=np.float64)
+    c = O.codec()
+    x = np.array([[0, 0, 0], [np.inf, 0, 0], [1e-30, 0, 0], [1e30, 0, 0], [1, 2, 3], [0, 0, 2]],
+                 dtype=np.float32)
+    h, excluded, st = O.error_hist(c, x, edges)
+    assert excluded == 4 and int(h[0].sum()) == 2
+    rng = np.random.default_rng(3)
+    v = rng.standard_normal((2000, 3)).astype(np.float32)
+    h, _, st = O.error_hist(c, v, edges)
+    for k in range(3):
+        per = [O.error_hist(c, v[i:i + 1], edges)[2][k, 0] for i in range(v.shape[0])]
+        idx = np.searchsorted(edges, np.array(per), side="right")
+        assert np.array_equal(np.bincount(idx, minlength=edges.size + 1), h[k])
+        assert abs(sum(per) - st[k, 0]) <= 1e-12 * abs(st[k, 0])
+
+
+def test_error_hist_radius_invariance():
+    """§2.3: the normalised mean error does not depend on the radius over [1e-8, 1e8]."""
+    edges = O.log_edges()
+    base = inputs.unit_sphere(200_000, 54).astype(np.float64)
+    means = [O.error_hist(O.codec(), (base * r).astype(np.float32), edges)[2][0, 0] / 200_000
+             for r in (1e-8, 1.0, 1e8)]
+    assert max(means) / min(means) < 1.01
