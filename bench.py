@@ -154,6 +154,35 @@ def bench_apply(torch, vc, inputs, k: int):
             "bound": "mfma", "mfma_floor_us": flop / 157.3e12 * 1e6, "hbm_floor_us": byts / 8e12 * 1e6}
 
 
+def bench_anisotropy(torch, vc, inputs, n: int = 1 << 25):
+    """Codec error statistics on the GPU (FP64 error norms) for von Mises-Fisher directions,
+    kappa in {1, 10, 100, 1000}, mean +z and (1,1,1)/sqrt(3), lognormal magnitudes."""
+    import numpy as np
+
+    c = vc.codec()
+    edges_np = 10.0 ** (-12.0 + np.arange(101, dtype=np.float64) / 10)
+    edges = torch.from_numpy(edges_np).to("cuda")
+    res = {"n": n, "edges": "10^(-12 + i/10), i = 0..100"}
+    for kappa in (1.0, 10.0, 100.0, 1000.0):
+        for mname, mean in (("z", (0.0, 0.0, 1.0)), ("diag", (1.0, 1.0, 1.0))):
+            x = inputs.vmf_torch(n, kappa, mean, seed=int(kappa) + (0 if mname == "z" else 7))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            h, ex, st = vc.error_hist(c, x, edges)
+            ms = (time.perf_counter() - t0) * 1e3
+            m = int(h[0].sum())
+            st = st.numpy()
+            rec = {"mean": [float(v) for v in st[:, 0] / m], "max": [float(v) for v in st[:, 2]],
+                   "rms": [float(v) for v in np.sqrt(st[:, 1] / m)], "excluded": ex, "ms": ms}
+            if mname == "z" and kappa in (1.0, 1000.0):
+                rec["hist_angle_nonzero"] = {f"{edges_np[i - 1]:.2e}": int(v) for i, v in
+                                             enumerate(h[1].tolist()) if v and i > 0}
+            res[f"kappa{int(kappa)}_{mname}"] = rec
+            del x
+    res["kinds"] = ["|x_hat-x|/|x|", "angle(x, x_hat)", "|r_hat-r|/r"]
+    return res
+
+
 BYTES_PER_VEC = {"axpy": 24, "dot": 16, "norm2": 8, "encode": 20}
 
 
@@ -328,6 +357,10 @@ def main():
         log("fused apply (200,000 elements, 150 x 125)")
         extras["fused_apply"] = bench_apply(torch, vc, inputs, k)
         log(f"fused apply: {extras['fused_apply']}")
+        log("anisotropy error statistics (vMF, 2^25 vectors each)")
+        extras["anisotropy"] = bench_anisotropy(torch, vc, inputs)
+        log(f"anisotropy: " + ", ".join(f"{k}: {v['mean'][0]:.3e}" for k, v in extras["anisotropy"].items()
+                                        if isinstance(v, dict)))
         log("batched segments (64 segments, 10^3..10^7 vectors)")
         extras["batch"] = bench_batch(torch, vc, inputs, k, args.precision)
         log(f"batch: {extras['batch']}")

@@ -57,6 +57,18 @@ vc_status vcx_batch_plan_run_separate_graph(vc_batch_plan* plan, hipStream_t str
 /* Number of tiles the plan's persistent kernel walks and its grid size (workgroups). */
 vc_status vcx_batch_plan_info(const vc_batch_plan* plan, uint64_t* total_tiles, uint32_t* grid);
 
+/* Error statistics of the codec over n float32 vectors xyz (device, AoS), the error measures of
+ * §2.2-§2.3 evaluated in double precision on the GPU: each finite non-zero vector is encoded by
+ * the library's encoder and decoded in FP64 (Eq. (a_inv), (cart2sphere), §2.5 inverse maps);
+ *   k = 0: |x_hat - x|/|x|,  k = 1: angle(x, x_hat),  k = 2: |r_hat - |x||/|x|.
+ * Vectors that are zero, non-finite, flush to the zero code or saturate are counted in
+ * counts[3 (nedges+1)] and left out.  edges: device, nedges ascending FP64 values,
+ * 1 <= nedges <= 256; bin = number of edges <= e.  counts: device uint64 [3 (nedges+1) + 1],
+ * counts[k (nedges+1) + bin].  stats: device double [9], stats[3k] = sum e, [3k+1] = sum e^2,
+ * [3k+2] = max e.  Deterministic; partials are allocated with hipMallocAsync on `stream`. */
+vc_status vcx_error_hist(const vc_codec* c, const float* xyz, size_t n, const double* edges, int nedges,
+                         uint64_t* counts, double* stats, hipStream_t stream);
+
 /* dst[0:bytes) = src[0:bytes): the attainable-bandwidth reference.  16-byte aligned. */
 vc_status vcb_copy(const void* src, void* dst, size_t bytes, hipStream_t stream);
 

@@ -71,6 +71,7 @@ _SIGS = {
     "vcx_load_tuning": ([C.c_char_p], C.c_int),
     "vcx_batch_plan_run_separate_graph": ([_vp, _vp], C.c_int),
     "vcx_batch_plan_info": ([_vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint32)], C.c_int),
+    "vcx_error_hist": ([C.POINTER(vc_codec), _vp, C.c_size_t, _vp, C.c_int, _vp, _vp, _vp], C.c_int),
 }
 
 
@@ -230,6 +231,21 @@ def vcb_copy(src, dst, stream=None):
     nbytes = src.numel() * src.element_size()
     _check(lib().vcb_copy(_ptr(src), _ptr(dst), nbytes, _stream(stream)), "vcb_copy")
     return dst
+
+
+def error_hist(c: vc_codec, xyz, edges, stream=None):
+    """(counts [3, nedges+1] int64, excluded, stats [3, 3] = (sum, sum of squares, max)) of the
+    codec's errors over the float32 vectors xyz [N, 3] (device); edges: float64 device tensor."""
+    torch = _torch()
+    _require(xyz, torch.float32, "error_hist xyz")
+    _require(edges, torch.float64, "error_hist edges")
+    ne = edges.numel()
+    counts = torch.empty(3 * (ne + 1) + 1, dtype=torch.int64, device=xyz.device)
+    stats = torch.empty(9, dtype=torch.float64, device=xyz.device)
+    _check(lib().vcx_error_hist(C.byref(c), _ptr(xyz), xyz.numel() // 3, _ptr(edges), ne, _ptr(counts),
+                                _ptr(stats), _stream(stream)), "vcx_error_hist")
+    cnt = counts.cpu()
+    return cnt[:-1].reshape(3, ne + 1), int(cnt[-1]), stats.cpu().reshape(3, 3)
 
 
 def set_stream_config(block: int, vpt: int, nt: int, precision: str = "both"):

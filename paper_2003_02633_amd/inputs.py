@@ -21,6 +21,8 @@ Workloads (shapes and distributions follow the paper's test settings: the unit b
 """
 from __future__ import annotations
 
+import math
+
 import numpy as np
 
 CHUNK = 1 << 22
@@ -132,6 +134,23 @@ def vmf(n: int, kappa: float, mean=(0.0, 0.0, 1.0), seed: int = 0, sigma: float 
         r = np.exp(sigma * g.standard_normal(m))[:, None]
         out[s:e] = (d * r).astype(np.float32)
     return out
+
+
+def vmf_torch(n: int, kappa: float, mean=(0.0, 0.0, 1.0), seed: int = 0, sigma: float = 2.0, device="cuda"):
+    """GPU-side draw of the ``vmf`` distribution (torch's seeded Philox generator), FP64 then FP32."""
+    import torch
+
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    R = torch.from_numpy(_rotation_to(np.asarray(mean, dtype=np.float64))).to(device)
+    xi = torch.rand(n, generator=g, dtype=torch.float64, device=device)
+    w = 1.0 + torch.log(xi + (1.0 - xi) * math.exp(-2.0 * kappa)) / kappa
+    w = w.clamp(-1.0, 1.0)
+    az = 2.0 * math.pi * torch.rand(n, generator=g, dtype=torch.float64, device=device)
+    sw = torch.sqrt(torch.clamp(1.0 - w * w, min=0.0))
+    d = torch.stack([sw * torch.cos(az), sw * torch.sin(az), w], dim=1) @ R.T
+    r = torch.exp(sigma * torch.randn(n, generator=g, dtype=torch.float64, device=device))[:, None]
+    return (d * r).to(torch.float32).contiguous()
 
 
 def gauss_legendre_nodes(k: int) -> np.ndarray:

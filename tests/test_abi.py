@@ -174,3 +174,13 @@ def test_tuning_cache_parsing(lib, tmp_path):
         for p, (b, v, t) in saved.items():
             vc.set_stream_config(b, v, t, p)
     assert vc.get_stream_config("f64") == saved["f64"]
+
+
+def test_error_hist_validation_without_device_work(lib):
+    P = C.byref(vc.codec())
+    f = _fake
+    assert lib.vcx_error_hist(P, f(0x10000), 8, f(0x20000), 0, f(0x30000), f(0x40000), None) == 1
+    assert lib.vcx_error_hist(P, f(0x10000), 8, f(0x20000), 257, f(0x30000), f(0x40000), None) == 1
+    assert lib.vcx_error_hist(P, None, 8, f(0x20000), 10, f(0x30000), f(0x40000), None) == 1
+    assert lib.vcx_error_hist(P, f(0x10000), 8, f(0x20004), 10, f(0x30000), f(0x40000), None) == 2
+    assert lib.vcx_error_hist(P, f(0x10000), 8, f(0x20000), 10, f(0x30004), f(0x40000), None) == 2
