@@ -552,10 +552,13 @@ VC_DI double angle_levels64(double num, double den, bool den_neg, double Kq_half
 {
   constexpr double T8 = 0.41421356237309503;      // tan(pi/8)
   const bool swap = num > den;
-  const double mx = swap ? num : den, mn = swap ? den : num;
+  const double mx = __builtin_fmax(num, den), mn = __builtin_fmin(num, den);
   const bool R = mn > T8 * mx;
-  const double nu = R ? mn - mx : mn;
-  const double de = R ? mn + mx : mx;             // > 0 except at the pole (caller fixes theta there)
+  // (nu, de) = R ? (mn - mx, mn + mx) : (mn, mx), as FMAs with a 0/1 factor (each one rounding,
+  // or exact when the factor is 0)
+  const double Rd = R ? 1.0 : 0.0;
+  const double nu = fma64_(-Rd, mx, mn);
+  const double de = fma64_(Rd, mn, mx);           // > 0 except at the pole (caller fixes theta there)
   const double rc = rcp64_(de);
   double b = nu * rc;
   b = fma64_(fma64_(-b, de, nu), rc, b);          // quotient to ~2^-48
