@@ -30,6 +30,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E spec
 ALPHA = 0.699999988079071      # float32(0.7)
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "axpy_n2p27_traffic.txt")
+PROFILE_VALU = os.path.join(ROOT, "profiles", "axpy_n2p27_valu.txt")
 KERNEL_SOURCES = ["paper_2003_02633_amd/csrc/vc_device.hpp", "paper_2003_02633_amd/csrc/vc_stream.hip",
                   "paper_2003_02633_amd/csrc/vc_coeffs.inc"]
 
@@ -46,21 +47,40 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic(n: int):
-    """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it was taken on the
-    current kernel sources and this N; otherwise None."""
-    if not os.path.exists(PROFILE_TRAFFIC):
+def _read_profile(path: str, n: int):
+    """key = value lines of a committed rocprofv3 summary, if it was taken on the current kernel
+    sources and this N; otherwise None."""
+    if not os.path.exists(path):
         return None
     kv = {}
-    with open(PROFILE_TRAFFIC) as f:
+    with open(path) as f:
         for line in f:
             if "=" in line and not line.startswith("#"):
                 k, v = line.split("=", 1)
                 kv[k.strip()] = v.strip()
-    if kv.get("kernel_hash") != kernel_hash() or int(kv.get("n_vectors", -1)) != n:
+    if kv.get("kernel_hash") != kernel_hash():
         return None
+    if "n_vectors" in kv and int(kv["n_vectors"]) != n:
+        return None
+    return kv
+
+
+def read_traffic(n: int):
+    """HBM bytes per launch from the committed rocprofv3 --pmc summary (FETCH_SIZE + WRITE_SIZE,
+    calibrated on a copy kernel), or None when the kernel changed since it was taken."""
+    kv = _read_profile(PROFILE_TRAFFIC, n)
     try:
-        return float(kv["traffic_bytes_per_launch"])
+        return float(kv["traffic_bytes_per_launch"]) if kv else None
+    except (KeyError, ValueError):
+        return None
+
+
+def read_valu(n: int):
+    """VALU figures of the same kernel (SQ_INSTS_VALU, SQ_ACTIVE_INST_VALU), or None."""
+    kv = _read_profile(PROFILE_VALU, n)
+    try:
+        return {"valu_instr_per_vector": float(kv["valu_instr_per_vector"]),
+                "valu_busy_frac": float(kv["valu_busy_frac"])} if kv else None
     except (KeyError, ValueError):
         return None
 
@@ -81,28 +101,34 @@ def timed(torch, fn, steps: int, warmup: int) -> float:
     return e0.elapsed_time(e1) / steps
 
 
-def cpu_baseline(torch, wa_dev, wb_dev, target_s: float = 10.0):
-    """Time the oracle's compressed axpy on the host, all cores, on a bounded prefix sample."""
+def cpu_baseline(torch, wa_dev, wb_dev, target_s: float = 12.0):
+    """Time the oracle's compressed axpy on the host, all cores, on a bounded sample: the first n
+    vectors of the benchmark operands (at most 2^25, 0.75 GiB of codes), passed over repeatedly
+    until about target_s seconds of CPU work have been timed."""
+    import math
+
     import numpy as np
 
     import oracle as O
 
     co = O.codec()
     threads = O.max_threads()
-    n_cal = 1 << 16
+    n_cal = 1 << 18
     wa = wa_dev[:n_cal].cpu().numpy().view(np.uint64)
     wb = wb_dev[:n_cal].cpu().numpy().view(np.uint64)
     t = time.perf_counter()
     O.axpy(co, ALPHA, wa, wb, threads)
     rate = n_cal / max(time.perf_counter() - t, 1e-6)
-    n = int(min(wa_dev.numel(), max(n_cal, min(1 << 25, rate * target_s))))
+    n = int(min(wa_dev.numel(), 1 << 25, max(n_cal, rate * target_s)))
+    reps = max(1, math.ceil(rate * target_s / n))
     wa = wa_dev[:n].cpu().numpy().view(np.uint64)
     wb = wb_dev[:n].cpu().numpy().view(np.uint64)
     t = time.perf_counter()
-    O.axpy(co, ALPHA, wa, wb, threads)
+    for _ in range(reps):
+        O.axpy(co, ALPHA, wa, wb, threads)
     dt = time.perf_counter() - t
-    return {"value": n / dt / 1e9, "unit": "Gvec/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {n} vectors of the benchmark operands; oracle compressed axpy "
+    return {"value": reps * n / dt / 1e9, "unit": "Gvec/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {n} vectors of the benchmark operands, {reps} passes; oracle compressed axpy "
                       f"(decode both, single-rounded FMA, encode), OpenMP over {threads} threads, {dt:.1f} s"}
 
 
@@ -397,7 +423,8 @@ def main():
         "error": err,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": read_traffic(N),
-                     "algorithmic_bytes_per_launch": 24 * N},
+                     "algorithmic_bytes_per_launch": 24 * N, "copy_GBs": extras.get("copy", {}).get("GBs"),
+                     "valu": read_valu(N)},
         "cpu_baseline": cpu,
         "extras": extras,
     }

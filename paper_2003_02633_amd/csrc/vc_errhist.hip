@@ -8,8 +8,8 @@
 // double-precision arithmetic of the path that does not concern the encoder itself.
 //
 // Histograms: bin = number of edges <= e (edges ascending, FP64, staged in LDS, binary search).
-// Each workgroup accumulates LDS counters and FP64 sums; per-workgroup partials are summed by a
-// second kernel in workgroup order, so the result is deterministic.
+// Each workgroup accumulates LDS counters and FP64 sums; a second kernel (one workgroup per
+// output slot) sums the per-workgroup partials in a fixed order, so the result is deterministic.
 #include "vc_internal.hpp"
 #include "../../include/vc_ext.h"
 
@@ -149,25 +149,33 @@ __global__ __launch_bounds__(EH_BS) void k_errhist(const float* __restrict__ xyz
   for (int i = threadIdx.x; i < nc; i += EH_BS) part_counts[(size_t)blockIdx.x * nc + i] = h[i];
 }
 
-// counts[j] = sum over workgroups of part_counts[g][j]; stats likewise (max for k % 3 == 2)
+// one workgroup per output slot j (counters 0 .. nc-1, then the 9 statistics): a fixed-order
+// sum (or max) over the per-workgroup partials -- strided per thread, then a fixed tree
 __global__ __launch_bounds__(EH_BS) void k_errhist_reduce(const uint32_t* __restrict__ part_counts,
                                                           const double* __restrict__ part_stats, int groups,
                                                           int nc, uint64_t* __restrict__ counts,
                                                           double* __restrict__ stats)
 {
-  for (int j = threadIdx.x; j < nc; j += EH_BS) {
-    uint64_t acc = 0;
-    for (int g = 0; g < groups; g++) acc += part_counts[(size_t)g * nc + j];
-    counts[j] = acc;
+  __shared__ double red[EH_BS];
+  const int j = blockIdx.x;
+  const bool is_count = j < nc;
+  const int k = j - nc;
+  const bool is_max = !is_count && (k % 3 == 2);
+  double v = 0.0;
+  for (int g = threadIdx.x; g < groups; g += EH_BS) {
+    const double p = is_count ? (double)part_counts[(size_t)g * nc + j] : part_stats[(size_t)g * 9 + k];
+    v = is_max ? fmax(v, p) : v + p;
   }
-  if (threadIdx.x < 9) {
-    const int k = threadIdx.x;
-    double v = 0.0;
-    for (int g = 0; g < groups; g++) {
-      const double p = part_stats[(size_t)g * 9 + k];
-      v = (k % 3 == 2) ? fmax(v, p) : v + p;
-    }
-    stats[k] = v;
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = EH_BS / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] = is_max ? fmax(red[threadIdx.x], red[threadIdx.x + off])
+                                                      : red[threadIdx.x] + red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (is_count) counts[j] = (uint64_t)red[0];   // exact: counts stay far below 2^53
+    else stats[k] = red[0];
   }
 }
 
@@ -213,8 +221,8 @@ extern "C" vc_status vcx_error_hist(const vc_codec* c, const float* xyz, size_t 
   pc = (uint32_t*)((char*)scratch + (size_t)(groups ? groups : 1) * 9 * sizeof(double));
   st = launch_errhist(R, xyz, n, edges, nedges, pc, ps, groups, stream);
   if (st == VC_SUCCESS) {
-    hipLaunchKernelGGL(k_errhist_reduce, dim3(1), dim3(EH_BS), 0, stream, (const uint32_t*)pc, (const double*)ps,
-                       groups, nc, counts, stats);
+    hipLaunchKernelGGL(k_errhist_reduce, dim3((unsigned)(nc + 9)), dim3(EH_BS), 0, stream, (const uint32_t*)pc,
+                       (const double*)ps, groups, nc, counts, stats);
     st = launch_status();
   }
   if (hipFreeAsync(scratch, stream) != hipSuccess && st == VC_SUCCESS) st = VC_ERROR_HIP;

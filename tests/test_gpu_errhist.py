@@ -3,7 +3,8 @@
 Contract: the GPU encodes with the library's encoder, so its codes may differ from the oracle's
 by one level inside the one-ulp window (counted here as n_diff).  Each such vector can move one
 count per histogram, so per histogram sum |h_gpu - h_oracle| <= 2 n_diff; the sums differ by at
-most n_diff times the largest per-vector error change (< 4e-5) plus FP64 rounding; the vectors
+most n_diff times the largest per-vector error change (< 4e-5) plus 1e-9 relative (the two FP64
+decodes differ in their sincospi/atan2 implementations by ~1e-16 of |x|); the vectors
 left out (zero, non-finite, flushed, saturated) agree exactly.
 """
 import sys
@@ -51,8 +52,10 @@ def _compare(torch, layout, mode, kw, xyz, label):
     for k in range(3):
         assert int(hg[k].sum()) == n
         assert int(np.abs(hg[k] - ho[k]).sum()) <= 2 * n_diff
-        assert abs(sg[k, 0] - so[k, 0]) <= n_diff * 4e-5 + 1e-10 * abs(so[k, 0])
-        assert abs(sg[k, 2] - so[k, 2]) <= (4e-5 if n_diff else 1e-12 * so[k, 2] + 1e-300)
+        # the two FP64 decodes use different sincospi/atan2 implementations: x_hat differs by
+        # ~1e-16 |x|, so each error value by ~1e-11 relative; 1e-9 relative covers it
+        assert abs(sg[k, 0] - so[k, 0]) <= n_diff * 4e-5 + 1e-9 * abs(so[k, 0])
+        assert abs(sg[k, 2] - so[k, 2]) <= (4e-5 if n_diff else 1e-9 * so[k, 2] + 1e-300)
     return sg / max(n, 1)
 
 
