@@ -110,6 +110,8 @@ struct Layout {
   static constexpr int emax = (int)emask - 1;         // all-ones exponent is reserved
   static constexpr bool keep_sub = (E_ == 8 && BIAS_ == 127);
   static constexpr uint64_t reserved = (uint64_t)emask << sh_e;
+  // largest finite magnitude: E = emax, M all ones (E and M fields only)
+  static constexpr uint64_t saturated = ((uint64_t)(emask - 1u) << sh_e) | (((1ull << M_) - 1ull) << sh_m);
   static_assert(S_ + E_ + M_ + P_ + T_ == 64, "layout must fill 64 bits");
   static_assert(M_ == 22 || M_ == 23, "mantissa of 22 or 23 bits");
 };
@@ -622,20 +624,31 @@ VC_DI uint64_t encode_vec64(float x, float y, float z, const Params& P)
   const uint32_t low = (uint32_t)rb0 & ((1u << drop) - 1u);
   bool amb = (low - (half - 256u)) < 512u;        // within 2^-44 of a rounding midpoint
   const uint64_t rb = (rb0 + half) & ~((1ull << drop) - 1ull);
-  int e_r = (int)(rb >> 52) - 1023;
-  uint32_t Mfield = (uint32_t)(rb >> drop) & ((1u << L::m) - 1u);
-  if (L::keep_sub) amb = amb || (e_r + L::bias <= 1);
-  if (amb) {
+  // code exponent E = e + bias lies in [1, emax]  <=>  rb in [rb_lo, rb_hi)
+  constexpr uint64_t rb_lo = (uint64_t)(1024 - L::bias) << 52;
+  constexpr uint64_t rb_hi = (uint64_t)(1024 - L::bias + L::emax) << 52;
+  if (L::keep_sub) amb = amb || rb < rb_lo + (1ull << 52);   // E <= 1: subnormal codes, exact path
+  uint64_t em;                                    // the code's E and M fields in place
+  if (!amb) {
+    if (rb < rb_lo) return 0ull;                  // underflow flushes to the zero code
+    // the FP64 exponent and fraction fields of rb moved to the code's E|M position, with the
+    // exponent re-biased (modulo 2^64 the bits above the field drop out)
+    constexpr int k = L::sh_e - 52;
+    static_assert(k > 0, "code exponent field above bit 52");
+    em = rb >= rb_hi ? L::saturated : (rb << k) - ((uint64_t)(1023 - L::bias) << L::sh_e);
+  } else {
     uint32_t j;
-    int g;
+    int g, e_r;
+    uint32_t Mfield;
     exact_norm_round(x, y, z, L::m + 1, L::keep_sub, j, g);
     if (j >= (1u << L::m)) { e_r = g + L::m; Mfield = j - (1u << L::m); }
     else { e_r = -L::bias; Mfield = j; }
+    int E = e_r + L::bias;
+    if (E < 1 && !(L::keep_sub && E == 0)) return 0ull;   // underflow flushes to the zero code
+    if (L::keep_sub && E == 0 && Mfield == 0u) return 0ull;
+    em = E > L::emax ? L::saturated                        // saturate, angles kept
+                     : ((uint64_t)(uint32_t)E << L::sh_e) | ((uint64_t)Mfield << L::sh_m);
   }
-  int E = e_r + L::bias;
-  if (E < 1 && !(L::keep_sub && E == 0)) return 0ull;   // underflow flushes to the zero code
-  if (L::keep_sub && E == 0 && Mfield == 0u) return 0ull;
-  if (E > L::emax) { E = L::emax; Mfield = (1u << L::m) - 1u; }   // saturate
 
   // ---- rho = sqrt(x^2 + y^2) to ~2^-47 (R2 + 2^-1000 == R2 unless R2 == 0)
   const double R2g = R2 + 0x1p-1000;
@@ -652,8 +665,9 @@ VC_DI uint64_t encode_vec64(float x, float y, float z, const Params& P)
     const double Qs = yneg ? -Q : Q;
     nth = (uint32_t)((int)P.base_t + (int)floor64_(P.odd_t ? Qs : Qs + 0.5));
   } else {
-    // n_theta_max odd: for y < 0, |Q| is never an integer, so floor(-|Q|) = -1 - floor(|Q|)
-    const int f = (int)floor64_(Q);
+    // n_theta_max odd: for y < 0, |Q| is never an integer, so floor(-|Q|) = -1 - floor(|Q|);
+    // |Q| >= 0, so the truncating conversion is the floor
+    const int f = (int)Q;
     nth = yneg ? (uint32_t)((int)P.base_t - 1 - f) : (uint32_t)((int)P.base_t + f);
   }
   if (R2 == 0.0) nth = P.base_t;                  // pole: theta = atan2(0, 0) = 0
@@ -666,13 +680,11 @@ VC_DI uint64_t encode_vec64(float x, float y, float z, const Params& P)
     const double m = compand64<MODE>(__builtin_fabs(Qc), P.invKc64, P);
     nph = (uint32_t)((int)((P.nmax_p + 1u) / 2u) + (int)floor64_(Qc < 0 ? -m : m));
   } else {
-    nph = (uint32_t)(int)floor64_(V + 0.5);
+    nph = (uint32_t)(int)(V + 0.5);               // V >= 0: truncation is the floor
   }
 
-  uint64_t lowf;
-  if (MODE == FRAC) lowf = (uint64_t)nph * (uint64_t)P.T + (uint64_t)nth;
-  else lowf = ((uint64_t)nph << L::t) | (uint64_t)nth;
-  return ((uint64_t)(uint32_t)E << L::sh_e) | ((uint64_t)Mfield << L::sh_m) | lowf;
+  if (MODE == FRAC) return em | ((uint64_t)nph * (uint64_t)P.T + (uint64_t)nth);
+  return ((uint64_t)nph << L::t) + (em | (uint64_t)nth);
 }
 
 // precision dispatch

@@ -54,8 +54,23 @@ def _workloads():
                         [-1e10, -1e-30, 0], [0, 0, -0.0], [-0.0, -0.0, 1], [1e-40, -1e-41, 0]],
                        dtype=np.float32)
     tiny = (g.standard_normal((2000, 3)) * 1e-39).astype(np.float32)
+    # magnitudes at and around the ends of every layout's range (flush, smallest code, the
+    # rounding midpoint below 2^47 that saturates, IEEE subnormals and overflow for e = 8)
+    radii = [2.0 ** -81, 2.0 ** -80, 2.0 ** -80 * (1 + 2.0 ** -23), 2.0 ** -79 * (1 - 2.0 ** -24), 2.0 ** -79,
+             1.5 * 2.0 ** -79, 2.0 ** 46 * (2 - 2.0 ** -22), 2.0 ** 46 * (2 - 2.0 ** -23),
+             2.0 ** 46 * (2 - 2.0 ** -24), 2.0 ** 47, 1e20, 3.0e38, 1.1754944e-38, 1e-40, 1.4e-45, 2.0 ** -126,
+             2.0 ** -127 * 1.5, 2.0 ** 127 * (2 - 2.0 ** -23)]
+    dirs = np.array([[1, 0, 0], [0.6, 0.8, 0], [0, 0, -1], [1, 2, 3]], dtype=np.float64)
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    with np.errstate(over="ignore"):
+        limits = (np.array(radii)[:, None, None] * dirs[None]).reshape(-1, 3).astype(np.float32)
+    limits = limits[np.isfinite(limits).all(axis=1)]
+    # norms beyond the largest float: saturate in the e = 8 layouts
+    limits = np.concatenate([limits, np.array([[3e38, 3e38, 0], [3.4e38, 1e38, -1e38], [-2e38, 2e38, 2e38]],
+                                              dtype=np.float32)])
     return [("gauss", inputs.gaussian_with_edges(20000, 0)), ("sphere_log", inputs.sphere_loguniform(60000, 1)),
-            ("crafted", crafted), ("tiny", tiny), ("vmf_pole", inputs.vmf(20000, 1000.0, seed=5))]
+            ("crafted", crafted), ("tiny", tiny), ("vmf_pole", inputs.vmf(20000, 1000.0, seed=5)),
+            ("limits", limits)]
 
 
 @pytest.mark.parametrize("layout,mode,kw", VARIANTS)
