@@ -101,7 +101,7 @@ def timed(torch, fn, steps: int, warmup: int) -> float:
     return e0.elapsed_time(e1) / steps
 
 
-def cpu_baseline(torch, wa_dev, wb_dev, target_s: float = 12.0):
+def cpu_baseline(torch, wa_dev, wb_dev, target_s: float = 15.0):
     """Time the oracle's compressed axpy on the host, all cores, on a bounded sample: the first n
     vectors of the benchmark operands (at most 2^25, 0.75 GiB of codes), passed over repeatedly
     until about target_s seconds of CPU work have been timed."""

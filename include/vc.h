@@ -125,8 +125,8 @@ vc_status vc_norm2(const vc_codec* c, const uint64_t* a, size_t n, float* d_out,
  * element e, out[e] (rows x 3, float32) = M (rows x cols, float32 row-major, device)
  * times decode(U[e]) (cols vectors, codes [n_elem][cols], device).  Contraction on
  * the matrix cores in single precision with single-precision accumulation.
- * 1 <= rows <= 256, 1 <= cols <= 256 and 4 ceil(cols/4) rows <= 20480 (the operator is staged
- * in LDS), else VC_ERROR_INVALID_VALUE. */
+ * 1 <= rows <= 256, 1 <= cols <= 256 and 4 ceil(cols/4) RS <= 20480, RS = rows rounded up to
+ * 24 mod 32 (the operator is staged in LDS with row stride RS), else VC_ERROR_INVALID_VALUE. */
 vc_status vc_fused_apply(const vc_codec* c, const float* M, int rows, int cols, const uint64_t* U,
                          float* out, size_t n_elem, hipStream_t stream);
 

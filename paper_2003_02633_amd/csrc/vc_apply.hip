@@ -7,13 +7,15 @@
 //
 // MFMA tiling (v_mfma_f32_16x16x4f32, FP32 in, FP32 accumulate):
 //   * a wave owns 16 elements; their x, y and z components form three 16-column B tiles;
-//   * rows are covered by MT 16-row tiles, so a wave keeps 3 MT accumulators (4 VGPRs each);
-//   * per K-step of 4, lane l decodes exactly one code -- element e0 + l%16, operand row
-//     k = s + KQ (l/16) (the K dimension is permuted so that each lane walks its element's
-//     codes in order) -- and feeds x, y, z straight into the three B fragments;
-//   * M is staged once per workgroup in LDS, transposed (A[k][row]) so the 16 lanes of a
-//     row group read consecutive addresses; rows beyond `rows` are never stored, columns
-//     k >= cols are zero in LDS and their B values are zero.
+//   * rows are covered by MT 16-row tiles, so a wave keeps 3 MT accumulators (4 registers each);
+//   * K is interleaved: at step s lane l (element e0 + l%16, quarter q = l/16) takes operand row
+//     k = 4s + q, so the four quarters of one element read 32 contiguous bytes of its codes; each
+//     lane decodes exactly one code per step and feeds x, y, z straight into the B fragments.
+//     The next step's code is loaded before the current step's MFMAs (software pipelining);
+//     operand rows k >= cols and elements past the end use the zero code, which decodes to 0;
+//   * M is staged once per workgroup in LDS, transposed (A[k][row], row stride RS = rows rounded
+//     up to 24 mod 32 words, so the four quarters hit different banks); rows beyond `rows` are
+//     read clamped and never stored.
 // A workgroup is 4 waves (64 elements per step), persistent over the element tiles.
 #include "vc_internal.hpp"
 
@@ -24,16 +26,26 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int APPLY_WAVES = 4;
 constexpr int APPLY_EPW = 16;      // elements per wave
 
+// A load the optimiser keeps where it is written (a relaxed wavefront-scope atomic load is an
+// ordinary global load, but it is not sunk to its use, so it stays one K-step ahead)
+__device__ __forceinline__ uint64_t ld_keep(const uint64_t* p)
+{
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+
+// LDS row stride: >= rows and == 24 (mod 32) words
+inline __host__ __device__ int apply_rs(int rows) { return rows + ((24 - rows % 32) + 32) % 32; }
+
 template <class L, int MODE, int MT>
 __global__ __launch_bounds__(64 * APPLY_WAVES) void k_apply(const float* __restrict__ M, int rows, int cols,
-                                                              int KQ, const uint64_t* __restrict__ U,
+                                                              int KS, int RS, const uint64_t* __restrict__ U,
                                                               float* __restrict__ out, size_t n_elem, Params P)
 {
-  extern __shared__ float As[];  // [4*KQ][rows], transposed, zero for k >= cols
-  const int KP = 4 * KQ;
-  for (int i = threadIdx.x; i < KP * rows; i += blockDim.x) {
-    const int k = i / rows, r = i - k * rows;
-    As[i] = (k < cols) ? M[(size_t)r * cols + k] : 0.0f;
+  extern __shared__ float As[];  // [4*KS][RS], transposed, zero for k >= cols
+  const int KP = 4 * KS;
+  for (int i = threadIdx.x; i < KP * RS; i += blockDim.x) {
+    const int k = i / RS, r = i - k * RS;
+    As[i] = (k < cols && r < rows) ? M[(size_t)r * cols + k] : 0.0f;
   }
   __syncthreads();
 
@@ -52,19 +64,32 @@ __global__ __launch_bounds__(64 * APPLY_WAVES) void k_apply(const float* __restr
 #pragma unroll
       for (int c = 0; c < 3; c++) acc[m][c] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 
-    for (int s = 0; s < KQ; s++) {
-      const int k = s + KQ * q;
-      float bx = 0.0f, by = 0.0f, bz = 0.0f;
-      if (e_ok && k < cols) decode_vec<L, MODE>(Ue[k], P, bx, by, bz);
-      const float* Ak = As + (size_t)k * rows;
+    // the code of step s + 1 is loaded while step s multiplies (from a clamped, always valid
+    // address; its validity is applied where it is used)
+    int kn = q;
+    uint64_t wraw = ld_keep(Ue + (kn < cols ? kn : cols - 1));
+    bool wok = e_ok && kn < cols;
+    for (int s = 0; s < KS; s++) {
+      const int k = kn;
+      const uint64_t w = wok ? wraw : 0ull;      // the zero code decodes to (0, 0, 0)
+      kn += 4;
+      wraw = ld_keep(Ue + (kn < cols ? kn : cols - 1));
+      wok = e_ok && kn < cols;
+      float bx, by, bz;
+      decode_vec<L, MODE>(w, P, bx, by, bz);
+      const float* Ak = As + k * RS;
+      float a[MT];
 #pragma unroll
       for (int m = 0; m < MT; m++) {
-        const int r = 16 * m + j;
-        const float a = Ak[r < rows ? r : rows - 1];
-        acc[m][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bx, acc[m][0], 0, 0, 0);
-        acc[m][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, by, acc[m][1], 0, 0, 0);
-        acc[m][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bz, acc[m][2], 0, 0, 0);
+        const int r = 16 * m + j;                 // rows past the end are read clamped, never stored
+        a[m] = Ak[r < rows ? r : rows - 1];
       }
+#pragma unroll
+      for (int m = 0; m < MT; m++) acc[m][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[m], bx, acc[m][0], 0, 0, 0);
+#pragma unroll
+      for (int m = 0; m < MT; m++) acc[m][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[m], by, acc[m][1], 0, 0, 0);
+#pragma unroll
+      for (int m = 0; m < MT; m++) acc[m][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[m], bz, acc[m][2], 0, 0, 0);
     }
     // D[i][jj] at lane jj + 16 (i/4), register i%4: this lane holds rows 16m + 4q + (0..3) of
     // element e, for the three components
@@ -90,8 +115,9 @@ template <class L, int MODE, int MT>
 static vc_status apply_mt(const Resolved& R, const float* M, int rows, int cols, const uint64_t* U, float* out,
                           size_t n_elem, hipStream_t s)
 {
-  const int KQ = (cols + 3) / 4;
-  const size_t lds = (size_t)4 * KQ * rows * sizeof(float);
+  const int KS = (cols + 3) / 4;
+  const int RS = apply_rs(rows);
+  const size_t lds = (size_t)4 * KS * RS * sizeof(float);
   int dev = 0, ncu = 256;
   if (hipGetDevice(&dev) == hipSuccess) {
     hipDeviceProp_t prop;
@@ -107,7 +133,7 @@ static vc_status apply_mt(const Resolved& R, const float* M, int rows, int cols,
           hipSuccess)
     return VC_ERROR_HIP;
   hipLaunchKernelGGL((k_apply<L, MODE, MT>), dim3((unsigned)grid), dim3(64 * APPLY_WAVES), lds, s, M, rows, cols,
-                     KQ, U, out, n_elem, R.P);
+                     KS, RS, U, out, n_elem, R.P);
   return launch_status();
 }
 
@@ -148,8 +174,8 @@ extern "C" vc_status vc_fused_apply(const vc_codec* c, const float* M, int rows,
   vc_status st = resolve(c, &R);
   if (st != VC_SUCCESS) return st;
   if (rows < 1 || rows > 256 || cols < 1 || cols > 256) return VC_ERROR_INVALID_VALUE;
-  // M^T staged in LDS: 4 ceil(cols/4) x rows floats must fit one workgroup's 80 KiB share
-  if ((size_t)4 * ((cols + 3) / 4) * rows * sizeof(float) > 80 * 1024) return VC_ERROR_INVALID_VALUE;
+  // M^T staged in LDS: 4 ceil(cols/4) x RS floats must fit one workgroup's 80 KiB share
+  if ((size_t)4 * ((cols + 3) / 4) * apply_rs(rows) * sizeof(float) > 80 * 1024) return VC_ERROR_INVALID_VALUE;
   if (n_elem == 0) return VC_SUCCESS;
   if (!M || !U || !out) return VC_ERROR_INVALID_VALUE;
   if (((uintptr_t)M & 3u) || ((uintptr_t)U & 7u) || ((uintptr_t)out & 3u)) return VC_ERROR_MISALIGNED;
