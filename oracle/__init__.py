@@ -92,6 +92,7 @@ def lib():
         L.vco_norm2.restype = C.c_double
         L.vco_apply.argtypes = [cp, vp, C.c_int, C.c_int, vp, vp, C.c_size_t, C.c_int]
         L.vco_max_threads.restype = C.c_int
+        L.vco_flux_div.argtypes = [cp, vp, C.c_int, C.c_int, vp, vp, C.c_size_t, C.c_int]
         L.vco_error_hist.argtypes = [cp, vp, C.c_size_t, vp, C.c_int, vp, vp, C.c_int]
         _lib = L
     return _lib
@@ -218,6 +219,20 @@ def apply(c: Codec, M, U, threads: int = 0) -> np.ndarray:
     out = np.empty((U.shape[0], rows, 3), dtype=np.float64)
     lib().vco_apply(C.byref(c), M.ctypes.data, rows, cols, U.ctypes.data, out.ctypes.data,
                     U.shape[0], threads)
+    return out
+
+
+def flux_div(c: Codec, D, F, threads: int = 0) -> np.ndarray:
+    """Alg. (fr_fdiv_comp) in FP64: D [3 ns][ns] (as float32), F codes [n_elem][ns][np];
+    returns [n_elem][ns][np]."""
+    D = np.ascontiguousarray(np.asarray(D, dtype=np.float32))
+    ns = D.shape[1]
+    assert D.shape[0] == 3 * ns
+    F = np.ascontiguousarray(np.asarray(F).astype(np.uint64, copy=False))
+    ne, ns2, npq = F.shape
+    assert ns2 == ns
+    out = np.empty((ne, ns, npq), dtype=np.float64)
+    lib().vco_flux_div(C.byref(c), D.ctypes.data, ns, npq, F.ctypes.data, out.ctypes.data, ne, threads)
     return out
 
 

@@ -653,3 +653,36 @@ void vco_error_hist(const vco_codec* c, const float* xyz, size_t n, const double
   free(loc);
   free(ls);
 }
+
+/* ------------------------------------------------------------------------- */
+/* divergence of a compressed flux (§4, Alg. fr_fdiv_comp)                    */
+/* ------------------------------------------------------------------------- */
+
+/* For every element i and solution point j the flux codes F[i][j][0..np) are decompressed to
+ * X (np rows of 3); every solution point k then receives d . X_p with
+ * d = (D[j][k], D[ns + j][k], D[2 ns + j][k]), D the 3 ns x ns divergence operator.  FP64
+ * accumulation in the algorithm's loop order. */
+void vco_flux_div(const vco_codec* c, const float* D, int ns, int np, const uint64_t* F, double* out,
+                  size_t n_elem, int nthreads)
+{
+  long long N = (long long)n_elem;
+#pragma omp parallel num_threads(nthr(nthreads))
+  {
+    double* X = (double*)malloc(sizeof(double) * 3 * (size_t)np);
+#pragma omp for schedule(static)
+    for (long long i = 0; i < N; i++) {
+      double* o = out + (size_t)i * ns * np;
+      for (int t = 0; t < ns * np; t++) o[t] = 0.0;
+      for (int j = 0; j < ns; j++) {
+        for (int p = 0; p < np; p++) vco_decode64(c, F[((size_t)i * ns + j) * np + p], X + 3 * p);
+        for (int k = 0; k < ns; k++) {
+          const double d0 = D[(size_t)j * ns + k];
+          const double d1 = D[(size_t)(ns + j) * ns + k];
+          const double d2 = D[(size_t)(2 * ns + j) * ns + k];
+          for (int p = 0; p < np; p++) o[(size_t)k * np + p] += d0 * X[3 * p] + d1 * X[3 * p + 1] + d2 * X[3 * p + 2];
+        }
+      }
+    }
+    free(X);
+  }
+}

@@ -89,6 +89,12 @@ int vco_max_threads(void);
  * (x_hat the FP64 decode, r_hat the code's magnitude).  Histogram bin = number of edges <= e
  * (edges ascending, 0..nedges): counts[k (nedges+1) + bin]; counts[3 (nedges+1)] = vectors left
  * out.  stats[3k] = sum e, stats[3k+1] = sum e^2, stats[3k+2] = max e. */
+/* Divergence of a compressed flux, Alg. (fr_fdiv_comp): out[i][k][p] = sum_j sum_c
+ * D[c ns + j][k] decode(F[i][j][p])[c], D float32 [3 ns][ns] row-major, F codes [n_elem][ns][np],
+ * out FP64 [n_elem][ns][np]. */
+void vco_flux_div(const vco_codec* c, const float* D, int ns, int np, const uint64_t* F, double* out,
+                  size_t n_elem, int nthreads);
+
 void vco_error_hist(const vco_codec* c, const float* xyz, size_t n, const double* edges, int nedges,
                     uint64_t* counts, double* stats, int nthreads);
 

@@ -18,6 +18,9 @@ Workloads (shapes and distributions follow the paper's test settings: the unit b
   * ``tgv_elements``         -- Taylor-Green velocity at Gauss-Legendre points of hex elements
   * ``uniform_matrix``       -- U[-1,1] operator entries
   * ``segments``             -- uneven segment table for the batched launch
+  * ``fr_derivative_1d`` / ``fr_div_operator`` -- nodal derivative operators of a hexahedral
+    flux-reconstruction element (tensor-product Lagrange basis on Gauss-Legendre points)
+  * ``euler_flux_tgv``       -- Euler flux rows (5 x 3 per point) of the Taylor-Green initial state
 """
 from __future__ import annotations
 
@@ -189,6 +192,81 @@ def tgv_elements(n_elem: int = 200_000, p: int = 4, grid=(100, 50, 40), seed: in
         vel = np.stack([u, v, w], axis=2) + noise * g.standard_normal((e - s, npts, 3))
         out[s:e] = vel.astype(np.float32)
     return out
+
+
+def fr_derivative_1d(p: int, h: float = 2.0) -> np.ndarray:
+    """d[a][b] = l_a'(x_b): derivative of the Lagrange basis polynomial a at Gauss-Legendre node b,
+    on an element of width h (reference width 2).  FP64, [p+1][p+1]."""
+    x = gauss_legendre_nodes(p + 1)
+    q = x.size
+    w = np.array([1.0 / np.prod([x[i] - x[m] for m in range(q) if m != i]) for i in range(q)])
+    d = np.empty((q, q))
+    for a in range(q):
+        for b in range(q):
+            d[a, b] = (w[a] / w[b]) / (x[b] - x[a]) if a != b else sum(1.0 / (x[a] - x[m]) for m in range(q) if m != a)
+    return d * (2.0 / h)
+
+
+def fr_div_operator(p: int, h=(2.0, 2.0, 2.0)) -> np.ndarray:
+    """Dense divergence operator of a hexahedral element, D[c n_s + j][k] = d l_j / d x_c at point
+    k, for the tensor-product basis; point index j = jx + q jy + q^2 jz, q = p + 1, n_s = q^3.
+    FP64, [3 n_s][n_s]."""
+    q = p + 1
+    ns = q ** 3
+    d = [fr_derivative_1d(p, hc) for hc in h]
+    eye = np.eye(q)
+    # kron order: the fastest index (x) is the last factor
+    Dx = np.kron(eye, np.kron(eye, d[0]))
+    Dy = np.kron(eye, np.kron(d[1], eye))
+    Dz = np.kron(d[2], np.kron(eye, eye))
+    return np.concatenate([Dx, Dy, Dz], axis=0).reshape(3 * ns, ns)
+
+
+def euler_flux_tgv(n_elem: int, p: int = 4, grid=(64, 64, 64), gamma: float = 1.4, U0: float = 1.0,
+                   rho0: float = 1.0, p0: float = 100.0, device=None):
+    """Inviscid flux rows of the Taylor-Green initial state (sec. 4, TGV: velocity U0 (f(x,y,z),
+    -f(y,x,z), 0), f = sin x cos y cos z, pressure p0 + rho0 U0^2/16 (cos 2x + cos 2y)(2 + cos 2z),
+    density from p rho0/p0) at the Gauss-Legendre solution points of hexahedral elements tiling
+    [0, 2 pi]^3 with ``grid`` elements per direction (element e at ix = e % gx, iy = (e / gx) % gy,
+    iz = e / (gx gy)), as the five rows of Eq. (eulerF):
+        (rho u, rho v, rho w), (rho u^2 + p, rho u v, rho u w), (rho u v, rho v^2 + p, rho v w),
+        (rho u w, rho v w, rho w^2 + p), (u (E + p), v (E + p), w (E + p)),
+    E = p / (gamma - 1) + rho |u|^2 / 2.  Returns float32 [n_elem][(p+1)^3][5][3] (a torch tensor on
+    ``device`` when given, else numpy).  Computed in FP64."""
+    import torch
+
+    gx, gy, gz = grid
+    if gx * gy * gz < n_elem:
+        raise ValueError("grid holds fewer elements than requested")
+    dev = torch.device(device) if device is not None else torch.device("cpu")
+    q = p + 1
+    xi = torch.from_numpy(0.5 * (gauss_legendre_nodes(q) + 1.0)).to(dev)
+    a = xi.view(1, 1, q).expand(q, q, q).reshape(-1)
+    b = xi.view(1, q, 1).expand(q, q, q).reshape(-1)
+    c = xi.view(q, 1, 1).expand(q, q, q).reshape(-1)
+    L = 2.0 * math.pi
+    out = torch.empty((n_elem, q ** 3, 5, 3), dtype=torch.float32, device=dev)
+    step = 1 << 14
+    for s in range(0, n_elem, step):
+        e = torch.arange(s, min(n_elem, s + step), device=dev, dtype=torch.float64)
+        ix, iy, iz = torch.remainder(e, gx), torch.remainder(torch.floor(e / gx), gy), torch.floor(e / (gx * gy))
+        X = (ix[:, None] + a[None]) * (L / gx)
+        Y = (iy[:, None] + b[None]) * (L / gy)
+        Z = (iz[:, None] + c[None]) * (L / gz)
+        u = U0 * torch.sin(X) * torch.cos(Y) * torch.cos(Z)
+        v = -U0 * torch.sin(Y) * torch.cos(X) * torch.cos(Z)
+        w = torch.zeros_like(u)
+        pr = p0 + rho0 * U0 * U0 / 16.0 * (torch.cos(2 * X) + torch.cos(2 * Y)) * (2.0 + torch.cos(2 * Z))
+        rho = pr * rho0 / p0
+        En = pr / (gamma - 1.0) + 0.5 * rho * (u * u + v * v + w * w)
+        rows = [(rho * u, rho * v, rho * w),
+                (rho * u * u + pr, rho * u * v, rho * u * w),
+                (rho * u * v, rho * v * v + pr, rho * v * w),
+                (rho * u * w, rho * v * w, rho * w * w + pr),
+                (u * (En + pr), v * (En + pr), w * (En + pr))]
+        blk = torch.stack([torch.stack(r, dim=-1) for r in rows], dim=-2)
+        out[s:s + blk.shape[0]] = blk.to(torch.float32)
+    return out if device is not None else out.numpy()
 
 
 def uniform_matrix(rows: int = 150, cols: int = 125, seed: int = 2) -> np.ndarray:

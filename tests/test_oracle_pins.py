@@ -635,3 +635,85 @@ def test_error_hist_radius_invariance():
     means = [O.error_hist(O.codec(), (base * r).astype(np.float32), edges)[2][0, 0] / 200_000
              for r in (1e-8, 1.0, 1e8)]
     assert max(means) / min(means) < 1.01
+
+
+# ---------------------------------------------------------------- divergence of a compressed flux
+def _poly_flux(p=4, grid=(3, 2, 2)):
+    """a flux whose rows are polynomials of degree <= 4 per coordinate, at the Gauss-Legendre
+    points of a grid of elements on [0, 1]^3, with its exact divergence (FP64)"""
+    q = p + 1
+    gx, gy, gz = grid
+    ne = gx * gy * gz
+    xi = 0.5 * (inputs.gauss_legendre_nodes(q) + 1.0)
+    a = np.tile(xi, q * q)
+    b = np.tile(np.repeat(xi, q), q)
+    c = np.repeat(xi, q * q)
+    e = np.arange(ne)
+    X = (e[:, None] % gx + a[None]) / gx
+    Y = ((e[:, None] // gx) % gy + b[None]) / gy
+    Z = (e[:, None] // (gx * gy) + c[None]) / gz
+    rows = [
+        ((X ** 3 + Y, Y * Y * Z + 2.0, Z ** 4 - X), (3 * X ** 2 + 2 * Y * Z + 4 * Z ** 3)),
+        ((X * Y * Z, -X ** 4, 0.5 * Y ** 2), (Y * Z)),
+        ((np.full_like(X, 7.0), Y ** 3 * X, -Z ** 2 * Y), (3 * Y ** 2 * X - 2 * Z * Y)),
+        ((X ** 2 * Z ** 2, Y - Z, X * Y + Z ** 3), (2 * X * Z ** 2 + 1 + 3 * Z ** 2)),
+        ((1e3 * X ** 2, 1e-3 * Y ** 4, -X ** 3 * Y), (2e3 * X + 4e-3 * Y ** 3)),
+    ]
+    F = np.stack([np.stack(r[0], axis=-1) for r in rows], axis=2)       # [ne][ns][5][3]
+    div = np.stack([r[1] for r in rows], axis=2)                        # [ne][ns][5]
+    return F, div, (1.0 / gx, 1.0 / gy, 1.0 / gz)
+
+
+def test_flux_div_polynomial_closed_form():
+    """Alg. (fr_fdiv_comp) with the hexahedral FR divergence operator differentiates a degree-4
+    polynomial flux exactly; with the flux compressed, the result stays within the propagated
+    codec bound: sum_{j,c} |D[c ns + j][k]| (1.73e-5 |F_jp| + 2^-24 |F_jp|) (Eq. v_error plus the
+    single-precision rounding of the input)."""
+    F, div, h = _poly_flux()
+    D = inputs.fr_div_operator(4, h)
+    D32 = D.astype(np.float32)
+    F32 = F.astype(np.float32)
+    co = O.codec()
+    W = O.encode(co, F32.reshape(-1, 3)).reshape(F.shape[:3])
+    got = O.flux_div(co, D32, W)
+    ns = D.shape[1]
+    Fn = np.linalg.norm(F, axis=3)                                       # [ne][ns][5]
+    absD = np.abs(D32.astype(np.float64)).reshape(3, ns, ns).sum(axis=0)   # [j][k]
+    bound = np.einsum("jk,ejp->ekp", absD, (1.73e-5 + 2.0 ** -24) * Fn) + 1e-9 * np.abs(div).max()
+    # the operator rounded to float32 contributes |D32 - D| |F|
+    bound += np.einsum("cjk,ejpc->ekp", np.abs(D32.astype(np.float64) - D).reshape(3, ns, ns), np.abs(F))
+    err = np.abs(got - div)
+    assert (err <= bound).all(), float((err / bound).max())
+    # a dropped component or a transposed operator is far outside the bound
+    assert np.abs(div).max() > 100 * bound.max()
+
+
+def test_flux_div_selector_operators():
+    """D with a single unit entry per column reduces Alg. (fr_fdiv_comp) to decode (§2.1
+    Eq. a_inv): D[c0 ns + j][k] = [j == k] gives out[i][k][p] = decode(F[i][k][p])[c0] exactly;
+    D[c0 ns + j0][k0] = 1 alone moves point j0's component to k0."""
+    co = O.codec()
+    ns, npq, ne = 8, 5, 3
+    rng = np.random.default_rng(17)
+    W = O.encode(co, rng.standard_normal((ne * ns * npq, 3)).astype(np.float32)).reshape(ne, ns, npq)
+    X = O.decode64(co, W.reshape(-1)).reshape(ne, ns, npq, 3)
+    for c0 in range(3):
+        D = np.zeros((3 * ns, ns), dtype=np.float32)
+        D[c0 * ns:(c0 + 1) * ns] = np.eye(ns)
+        assert np.array_equal(O.flux_div(co, D, W), X[..., c0])
+    D = np.zeros((3 * ns, ns), dtype=np.float32)
+    D[2 * ns + 5, 1] = 1.0
+    out = O.flux_div(co, D, W)
+    assert np.array_equal(out[:, 1], X[:, 5, :, 2]) and not out[:, [0, 2, 3, 4, 5, 6, 7]].any()
+
+
+def test_flux_div_linearity():
+    co = O.codec()
+    ns, npq = 27, 5
+    rng = np.random.default_rng(18)
+    W = O.encode(co, rng.standard_normal((2 * ns * npq, 3)).astype(np.float32)).reshape(2, ns, npq)
+    A = rng.uniform(-1, 1, (3 * ns, ns)).astype(np.float32)
+    B = rng.uniform(-1, 1, (3 * ns, ns)).astype(np.float32)
+    lhs = O.flux_div(co, A + B, W)   # exact float sums of small uniforms (one rounding each)
+    rhs = O.flux_div(co, A, W) + O.flux_div(co, B, W)
+    assert np.abs(lhs - rhs).max() <= 1e-6 * np.abs(rhs).max()
