@@ -209,6 +209,32 @@ def bench_anisotropy(torch, vc, inputs, n: int = 1 << 25):
     return res
 
 
+def bench_flux_div(torch, vc, inputs, k: int, grid=(64, 64, 64), p: int = 4):
+    """Divergence of the Taylor-Green Euler flux (step 10 of the FR right-hand side, Alg.
+    fr_fdiv_comp) on a grid of p = 4 hexahedra: compressed flux codes vs the same kernel on
+    float32 fluxes.  Algorithmic bytes per element: 125 x 5 codes (5,000 B) or 125 x 5 x 3 floats
+    (7,500 B) in, 125 x 5 floats (2,500 B) out -- the 9.77 KiB and ratio 0.75 of Table (mem_usage),
+    step 10, k = 4."""
+    import math
+
+    import numpy as np
+
+    n = grid[0] * grid[1] * grid[2]
+    q = p + 1
+    c = vc.codec()
+    d = torch.from_numpy(np.stack([inputs.fr_derivative_1d(p, 2 * math.pi / g) for g in grid]).astype(np.float32)).to("cuda")
+    F = inputs.euler_flux_tgv(n, p, grid=grid, device="cuda")
+    W = vc.vc_encode(c, F.view(-1, 3)).view(n, q ** 3, 5)
+    out = torch.empty((n, q ** 3, 5), dtype=torch.float32, device="cuda")
+    ms_c = timed(torch, lambda: vc.vc_flux_div_tp(c, d, W, out), k, 2)
+    ms_u = timed(torch, lambda: vc.vcb_flux_div_tp_f32(d, F, out), k, 2)
+    bc, bu = 7500.0 * n, 10000.0 * n
+    del F, W, out
+    return {"elements": n, "p": p, "equations": 5, "compressed_ms": ms_c, "uncompressed_ms": ms_u,
+            "speedup": ms_u / ms_c, "ideal_speedup_bytes": bu / bc,
+            "compressed_GBs": bc / (ms_c * 1e-3) / 1e9, "uncompressed_GBs": bu / (ms_u * 1e-3) / 1e9}
+
+
 BYTES_PER_VEC = {"axpy": 24, "dot": 16, "norm2": 8, "encode": 20}
 
 
@@ -383,6 +409,9 @@ def main():
         log("fused apply (200,000 elements, 150 x 125)")
         extras["fused_apply"] = bench_apply(torch, vc, inputs, k)
         log(f"fused apply: {extras['fused_apply']}")
+        log("flux divergence (TGV Euler flux, 64^3 p=4 hexahedra)")
+        extras["flux_div"] = bench_flux_div(torch, vc, inputs, k)
+        log(f"flux divergence: {extras['flux_div']}")
         log("anisotropy error statistics (vMF, 2^25 vectors each)")
         extras["anisotropy"] = bench_anisotropy(torch, vc, inputs)
         log(f"anisotropy: " + ", ".join(f"{k}: {v['mean'][0]:.3e}" for k, v in extras["anisotropy"].items()

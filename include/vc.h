@@ -130,6 +130,20 @@ vc_status vc_norm2(const vc_codec* c, const uint64_t* a, size_t n, float* d_out,
 vc_status vc_fused_apply(const vc_codec* c, const float* M, int rows, int cols, const uint64_t* U,
                          float* out, size_t n_elem, hipStream_t stream);
 
+/* Divergence of a compressed flux on hexahedral flux-reconstruction elements, Alg. (fr_fdiv_comp)
+ * of §4 (step 10 of the FR right-hand side): for element i, solution point k and equation p,
+ *   out[i][k][p] = sum_j sum_c D[c ns + j][k] decode(F[i][j][p])[c],
+ * with the tensor-product divergence operator of q = p_FR + 1 Gauss-Legendre points per
+ * direction, ns = q^3, point index j = jx + q jy + q^2 jz, given by its 1D factors:
+ * D[c ns + j][k] = d[c][j_c][k_c] when the two other coordinates of j and k agree, else 0.
+ *   d   : device float32 [3][q][q], d[c][a][b] = derivative in direction c of the basis
+ *         polynomial of node a, at node b (element scaling included);
+ *   F   : device codes [n_elem][ns][np], one row of the np x 3 flux tensor per code (Eq. eulerF);
+ *   out : device float32 [n_elem][ns][np], must not overlap F.
+ * 2 <= q <= 6, 1 <= np <= 8.  Single-precision decode and accumulation. */
+vc_status vc_flux_div_tp(const vc_codec* c, const float* d, int q, int np, const uint64_t* F, float* out,
+                         size_t n_elem, hipStream_t stream);
+
 /* ---- batched persistent launch over a segment table ---- */
 typedef enum { VC_OP_AXPY = 0, VC_OP_DOT = 1, VC_OP_NORM2 = 2, VC_OP_ENCODE = 3 } vc_op;
 

@@ -69,6 +69,11 @@ vc_status vcx_batch_plan_info(const vc_batch_plan* plan, uint64_t* total_tiles, 
 vc_status vcx_error_hist(const vc_codec* c, const float* xyz, size_t n, const double* edges, int nedges,
                          uint64_t* counts, double* stats, hipStream_t stream);
 
+/* vc_flux_div_tp on an uncompressed float32 flux F [n_elem][ns][np][3] (the same kernel reading
+ * floats): the baseline the compressed flux is compared with. */
+vc_status vcb_flux_div_tp_f32(const float* d, int q, int np, const float* F, float* out, size_t n_elem,
+                              hipStream_t stream);
+
 /* dst[0:bytes) = src[0:bytes): the attainable-bandwidth reference.  16-byte aligned. */
 vc_status vcb_copy(const void* src, void* dst, size_t bytes, hipStream_t stream);
 

@@ -71,6 +71,8 @@ _SIGS = {
     "vcx_load_tuning": ([C.c_char_p], C.c_int),
     "vcx_batch_plan_run_separate_graph": ([_vp, _vp], C.c_int),
     "vcx_batch_plan_info": ([_vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint32)], C.c_int),
+    "vc_flux_div_tp": ([C.POINTER(vc_codec), _vp, C.c_int, C.c_int, _vp, _vp, C.c_size_t, _vp], C.c_int),
+    "vcb_flux_div_tp_f32": ([_vp, C.c_int, C.c_int, _vp, _vp, C.c_size_t, _vp], C.c_int),
     "vcx_error_hist": ([C.POINTER(vc_codec), _vp, C.c_size_t, _vp, C.c_int, _vp, _vp, _vp], C.c_int),
 }
 
@@ -231,6 +233,33 @@ def vcb_copy(src, dst, stream=None):
     nbytes = src.numel() * src.element_size()
     _check(lib().vcb_copy(_ptr(src), _ptr(dst), nbytes, _stream(stream)), "vcb_copy")
     return dst
+
+
+def vc_flux_div_tp(c: vc_codec, d, F, out=None, stream=None):
+    """Alg. (fr_fdiv_comp) on hexahedra: d float32 [3][q][q] (device), F int64 codes
+    [n_elem][q^3][np] (device); returns float32 [n_elem][q^3][np]."""
+    torch = _torch()
+    _require(d, torch.float32, "vc_flux_div_tp d")
+    _require(F, torch.int64, "vc_flux_div_tp F")
+    q = d.shape[-1]
+    ne, ns, npq = F.shape
+    if out is None:
+        out = torch.empty((ne, ns, npq), dtype=torch.float32, device=F.device)
+    _check(lib().vc_flux_div_tp(C.byref(c), _ptr(d), q, npq, _ptr(F), _ptr(out), ne, _stream(stream)),
+           "vc_flux_div_tp")
+    return out
+
+
+def vcb_flux_div_tp_f32(d, F, out=None, stream=None):
+    """uncompressed baseline: F float32 [n_elem][q^3][np][3]"""
+    torch = _torch()
+    q = d.shape[-1]
+    ne, ns, npq, _ = F.shape
+    if out is None:
+        out = torch.empty((ne, ns, npq), dtype=torch.float32, device=F.device)
+    _check(lib().vcb_flux_div_tp_f32(_ptr(d), q, npq, _ptr(F), _ptr(out), ne, _stream(stream)),
+           "vcb_flux_div_tp_f32")
+    return out
 
 
 def error_hist(c: vc_codec, xyz, edges, stream=None):

@@ -184,3 +184,15 @@ def test_error_hist_validation_without_device_work(lib):
     assert lib.vcx_error_hist(P, None, 8, f(0x20000), 10, f(0x30000), f(0x40000), None) == 1
     assert lib.vcx_error_hist(P, f(0x10000), 8, f(0x20004), 10, f(0x30000), f(0x40000), None) == 2
     assert lib.vcx_error_hist(P, f(0x10000), 8, f(0x20000), 10, f(0x30004), f(0x40000), None) == 2
+
+
+def test_flux_div_validation_without_device_work(lib):
+    P = C.byref(vc.codec())
+    f = _fake
+    assert lib.vc_flux_div_tp(P, f(0x10000), 7, 5, f(0x20000), f(0x80000000), 4, None) == 1
+    assert lib.vc_flux_div_tp(P, f(0x10000), 5, 0, f(0x20000), f(0x80000000), 4, None) == 1
+    assert lib.vc_flux_div_tp(P, f(0x10000), 5, 5, f(0x20004), f(0x80000000), 4, None) == 2
+    assert lib.vc_flux_div_tp(P, f(0x10000), 5, 5, f(0x20000), f(0x20000 + 64), 4, None) == 7
+    assert lib.vc_flux_div_tp(P, None, 5, 5, f(0x20000), f(0x80000000), 4, None) == 1
+    assert lib.vc_flux_div_tp(P, None, 5, 5, None, None, 0, None) == 0
+    assert lib.vcb_flux_div_tp_f32(f(0x10000), 5, 5, f(0x20002), f(0x80000000), 4, None) == 2
