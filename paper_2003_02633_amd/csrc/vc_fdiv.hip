@@ -9,11 +9,13 @@
 //   div_kp = sum_a d_0[a][kx] X_(a,ky,kz)p.x + sum_a d_1[a][ky] X_(kx,a,kz)p.y
 //          + sum_a d_2[a][kz] X_(kx,ky,a)p.z.
 //
-// A workgroup takes EPW elements: it streams their codes (coalesced, non-temporal), decodes each
-// code once into LDS (float AoS, the code order), then makes three passes -- one thread per line
-// of q points -- that read q flux components and write (x pass) or add (y, z passes) q outputs
-// in an LDS accumulator, which is finally stored coalesced.  The derivative coefficients are
-// uniform across threads and live in scalar registers.  The same kernel reads plain float32
+// A workgroup takes EPW elements and makes three passes, one thread per line of q points:
+//   x: load the line's q codes (all in flight at once), decode each once, apply d_0 into an LDS
+//      accumulator and keep the y and z components in LDS;
+//   y: add d_1 along the y lines;
+//   z: add d_2 along the z lines and store -- for a z line, consecutive lanes (equation, then x,
+//      then y) hold consecutive outputs, so the stores are coalesced.
+// The derivative coefficients are uniform across threads.  The same kernel reads plain float32
 // fluxes as the uncompressed baseline.
 #include "vc_internal.hpp"
 #include "../../include/vc_ext.h"
@@ -21,9 +23,7 @@
 namespace vc {
 
 constexpr int FD_BS = 256;
-constexpr int FD_U = 8;      // loads in flight per thread
 
-typedef float f32x2 __attribute__((ext_vector_type(2)));
 
 template <class L, int MODE, int Q, bool CODES>
 __global__ __launch_bounds__(FD_BS) void k_fdiv_tp(const float* __restrict__ d, int NP, uint32_t np_rcp,
@@ -33,97 +33,138 @@ __global__ __launch_bounds__(FD_BS) void k_fdiv_tp(const float* __restrict__ d, 
   constexpr int Q2 = Q * Q, Q3 = Q * Q * Q;
   extern __shared__ float sm[];
   const int per = Q3 * NP;                    // flux rows (= outputs) per element
-  float* Xs = sm;                             // [EPW][Q3][NP][3]
-  float* Os = sm + (size_t)3 * EPW * per;     // [EPW][Q3][NP]
-  float dc[3][Q][Q];
-#pragma unroll
-  for (int c = 0; c < 3; c++)
-#pragma unroll
-    for (int a = 0; a < Q; a++)
-#pragma unroll
-      for (int b = 0; b < Q; b++) dc[c][a][b] = d[(c * Q + a) * Q + b];
+  float* Ys = sm;                             // [EPW][Q3][NP] y components
+  float* Zs = sm + (size_t)EPW * per;         // [EPW][Q3][NP] z components
+  float* Os = sm + (size_t)2 * EPW * per;     // [EPW][Q3][NP] accumulator
+  // the 3 q x q derivative coefficients, staged once; each pass reads its own q x q block with
+  // uniform (broadcast) LDS reads right before use, so only q^2 of them are live at a time
+  __shared__ float dsh[3 * Q2];
+  for (int i = threadIdx.x; i < 3 * Q2; i += FD_BS) dsh[i] = d[i];
+  __syncthreads();
+  // Lines l = ((e Q + u) Q + v) NP + p, (u, v) the two coordinates that stay fixed along the
+  // line; rows of line position a: x (a, v, u) = rx + a NP, y (v, a, u) = ry + a Q NP,
+  // z (v, u, a) = rz + a Q^2 NP.
+  auto bases = [&](int l, int& rx, int& ry, int& rz) {
+    const int t = (int)(((uint32_t)l * np_rcp) >> 20);   // l / NP, exact for l < 2^20 / NP
+    const int p = l - t * NP;
+    const int v = t % Q, u = (t / Q) % Q, e = t / Q2;
+    rx = (e * Q3 + Q * v + Q2 * u) * NP + p;
+    ry = (e * Q3 + v + Q2 * u) * NP + p;
+    rz = (e * Q3 + v + Q * u) * NP + p;
+  };
+  // a thread's first line (l = threadIdx.x) is the same in every group: its bases are computed once
+  int rx0, ry0, rz0;
+  bases(threadIdx.x, rx0, ry0, rz0);
 
   const size_t ngroups = (n_elem + EPW - 1) / EPW;
   for (size_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
     const size_t e0 = g * (size_t)EPW;
     const int ne = (int)((n_elem - e0) < (size_t)EPW ? (n_elem - e0) : (size_t)EPW);
-    const int nrows = ne * per;
-    // ---- load and decode: FD_U loads per thread are issued before any is used, so one memory
-    // latency is paid per batch rather than per row
-    if constexpr (CODES) {
-      const uint64_t* F = (const uint64_t*)Fv + e0 * per;
-      for (int i0 = threadIdx.x; i0 < nrows; i0 += FD_BS * FD_U) {
-        uint64_t w[FD_U];
-#pragma unroll
-        for (int u = 0; u < FD_U; u++) {
-          const int i = i0 + u * FD_BS;
-          w[u] = i < nrows ? __builtin_nontemporal_load(F + i) : 0ull;
-        }
-#pragma unroll
-        for (int u = 0; u < FD_U; u++) {
-          const int i = i0 + u * FD_BS;
-          if (i < nrows) {
-            float x, y, z;
-            decode_vec<L, MODE>(w[u], P, x, y, z);
-            Xs[3 * i] = x; Xs[3 * i + 1] = y; Xs[3 * i + 2] = z;
-          }
-        }
-      }
-    } else {
-      const float* F = (const float*)Fv + e0 * per * 3;
-      const int nf = 3 * nrows;
-      if ((((uintptr_t)F) & 7u) == 0) {
-        const f32x2* F2 = (const f32x2*)F;
-        const int n2 = nf / 2;
-        for (int i0 = threadIdx.x; i0 < n2; i0 += FD_BS * FD_U) {
-          f32x2 v[FD_U];
-#pragma unroll
-          for (int u = 0; u < FD_U; u++) {
-            const int i = i0 + u * FD_BS;
-            v[u] = i < n2 ? __builtin_nontemporal_load(F2 + i) : f32x2{0.0f, 0.0f};
-          }
-#pragma unroll
-          for (int u = 0; u < FD_U; u++) {
-            const int i = i0 + u * FD_BS;
-            if (i < n2) { Xs[2 * i] = v[u][0]; Xs[2 * i + 1] = v[u][1]; }
-          }
-        }
-        if (threadIdx.x == 0 && (nf & 1)) Xs[nf - 1] = F[nf - 1];
-      } else {
-        for (int i = threadIdx.x; i < nf; i += FD_BS) Xs[i] = __builtin_nontemporal_load(F + i);
-      }
-    }
-    __syncthreads();
-    // ---- three line passes; line l = ((e Q + u) Q + v) NP + p, (u, v) the two fixed coordinates
     const int nlines = ne * Q2 * NP;
+    const uint64_t* Fc = (const uint64_t*)Fv + e0 * per;    // this group's rows (uniform base)
+    const float* Ff = (const float*)Fv + e0 * per * 3;
+    float* og = out + e0 * per;
+
+    // ---- x: load and decode a line of q rows, apply d_0, keep y and z for the other passes
+    {
+      float dx[Q][Q];   // this pass's coefficients (uniform LDS reads)
 #pragma unroll
-    for (int c = 0; c < 3; c++) {
-      for (int l = threadIdx.x; l < nlines; l += FD_BS) {
-        // l / NP as (l * ceil(2^20 / NP)) >> 20, exact for l < 2^20 / NP (here l < 2^12)
-        const int t = (int)(((uint32_t)l * np_rcp) >> 20);
-        const int p = l - t * NP;
-        const int v = t % Q, u = (t / Q) % Q, e = t / Q2;
-        // point index of line position a: x pass (a, v, u), y pass (v, a, u), z pass (v, u, a)
-        const int base = e * Q3 + (c == 0 ? Q * v + Q2 * u : c == 1 ? v + Q2 * u : v + Q * u);
-        const int stride = c == 0 ? 1 : c == 1 ? Q : Q2;
-        float f[Q];
+      for (int a = 0; a < Q; a++)
 #pragma unroll
-        for (int a = 0; a < Q; a++) f[a] = Xs[((base + a * stride) * NP + p) * 3 + c];
+        for (int b = 0; b < Q; b++) dx[a][b] = dsh[a * Q + b];
+      auto xline = [&](int r0) {
+        float fx[Q];
+        if constexpr (CODES) {
+          uint64_t w[Q];
+#pragma unroll
+          for (int a = 0; a < Q; a++)
+            w[a] = __builtin_nontemporal_load((const uint64_t*)((const char*)Fc + (uint32_t)(r0 + a * NP) * 8u));
+#pragma unroll
+          for (int a = 0; a < Q; a++) {
+            float y, z;
+            decode_vec<L, MODE>(w[a], P, fx[a], y, z);
+            Ys[r0 + a * NP] = y;
+            Zs[r0 + a * NP] = z;
+          }
+        } else {
+          float y[Q], z[Q];
+#pragma unroll
+          for (int a = 0; a < Q; a++) {
+            const float* f = (const float*)((const char*)Ff + (uint32_t)(r0 + a * NP) * 12u);
+            fx[a] = __builtin_nontemporal_load(f);
+            y[a] = __builtin_nontemporal_load(f + 1);
+            z[a] = __builtin_nontemporal_load(f + 2);
+          }
+#pragma unroll
+          for (int a = 0; a < Q; a++) { Ys[r0 + a * NP] = y[a]; Zs[r0 + a * NP] = z[a]; }
+        }
 #pragma unroll
         for (int b = 0; b < Q; b++) {
           float s = 0.0f;
 #pragma unroll
-          for (int a = 0; a < Q; a++) s = __builtin_fmaf(dc[c][a][b], f[a], s);
-          float* o = Os + (base + b * stride) * NP + p;
-          *o = c == 0 ? s : *o + s;
+          for (int a = 0; a < Q; a++) s = __builtin_fmaf(dx[a][b], fx[a], s);
+          Os[r0 + b * NP] = s;
         }
+      };
+      for (int l = threadIdx.x; l < nlines; l += FD_BS) {
+        int rx = rx0, ry = ry0, rz = rz0;
+        if (l != (int)threadIdx.x) bases(l, rx, ry, rz);
+        xline(rx);
       }
-      __syncthreads();
     }
-    // ---- store
-    float* og = out + e0 * per;
-    for (int i = threadIdx.x; i < nrows; i += FD_BS) __builtin_nontemporal_store(Os[i], og + i);
-    __syncthreads();   // Xs / Os are reused by the next group
+    __syncthreads();
+    // ---- y: add d_1 along the y lines
+    {
+      float dy[Q][Q];
+#pragma unroll
+      for (int a = 0; a < Q; a++)
+#pragma unroll
+        for (int b = 0; b < Q; b++) dy[a][b] = dsh[Q2 + a * Q + b];
+      auto yline = [&](int r0) {
+        float f[Q];
+#pragma unroll
+        for (int a = 0; a < Q; a++) f[a] = Ys[r0 + a * Q * NP];
+#pragma unroll
+        for (int b = 0; b < Q; b++) {
+          float s = 0.0f;
+#pragma unroll
+          for (int a = 0; a < Q; a++) s = __builtin_fmaf(dy[a][b], f[a], s);
+          Os[r0 + b * Q * NP] += s;
+        }
+      };
+      for (int l = threadIdx.x; l < nlines; l += FD_BS) {
+        int rx = rx0, ry = ry0, rz = rz0;
+        if (l != (int)threadIdx.x) bases(l, rx, ry, rz);
+        yline(ry);
+      }
+    }
+    __syncthreads();
+    // ---- z: add d_2 along the z lines and store (consecutive lanes write consecutive outputs)
+    {
+      float dz[Q][Q];
+#pragma unroll
+      for (int a = 0; a < Q; a++)
+#pragma unroll
+        for (int b = 0; b < Q; b++) dz[a][b] = dsh[2 * Q2 + a * Q + b];
+      auto zline = [&](int r0) {
+        float f[Q];
+#pragma unroll
+        for (int a = 0; a < Q; a++) f[a] = Zs[r0 + a * Q2 * NP];
+#pragma unroll
+        for (int b = 0; b < Q; b++) {
+          float s = Os[r0 + b * Q2 * NP];
+#pragma unroll
+          for (int a = 0; a < Q; a++) s = __builtin_fmaf(dz[a][b], f[a], s);
+          __builtin_nontemporal_store(s, (float*)((char*)og + (uint32_t)(r0 + b * Q2 * NP) * 4u));
+        }
+      };
+      for (int l = threadIdx.x; l < nlines; l += FD_BS) {
+        int rx = rx0, ry = ry0, rz = rz0;
+        if (l != (int)threadIdx.x) bases(l, rx, ry, rz);
+        zline(rz);
+      }
+    }
+    __syncthreads();   // Ys / Zs / Os are reused by the next group
   }
 }
 
@@ -134,7 +175,7 @@ static inline int fdiv_epw(int q, int np)
   return e < 1 ? 1 : e;
 }
 
-static inline size_t fdiv_lds(int q, int np) { return (size_t)4 * fdiv_epw(q, np) * q * q * q * np * sizeof(float); }
+static inline size_t fdiv_lds(int q, int np) { return (size_t)3 * fdiv_epw(q, np) * q * q * q * np * sizeof(float); }
 
 template <class L, int MODE, int Q, bool CODES>
 static vc_status fdiv_q(const Resolved& R, const float* d, int np, const void* F, float* out, size_t n_elem,
