@@ -235,6 +235,32 @@ def bench_flux_div(torch, vc, inputs, k: int, grid=(64, 64, 64), p: int = 4):
             "compressed_GBs": bc / (ms_c * 1e-3) / 1e9, "uncompressed_GBs": bu / (ms_u * 1e-3) / 1e9}
 
 
+def bench_gather(torch, vc, k: int, n: int = 1 << 26):
+    """Indexed decode out[i] = decode(codes[idx[i]]) vs the float32 gather of the same vectors, for
+    the identity, face-sized blocks (25 consecutive points, the flux points of one face of a p = 4
+    hexahedron) in shuffled order, and a random permutation."""
+    c = vc.codec()
+    g = torch.Generator(device="cuda")
+    g.manual_seed(41)
+    x = torch.randn((n, 3), generator=g, dtype=torch.float32, device="cuda")
+    w = vc.vc_encode(c, x)
+    out = torch.empty_like(x)
+    nb = n // 25
+    blocks = torch.randperm(nb, generator=g, device="cuda").to(torch.int32)
+    face = (blocks[:, None] * 25 + torch.arange(25, device="cuda", dtype=torch.int32)[None]).reshape(-1)
+    pats = {"identity": torch.arange(n, device="cuda", dtype=torch.int32),
+            "face_blocks": torch.cat([face, torch.arange(nb * 25, n, device="cuda", dtype=torch.int32)]),
+            "random": torch.randperm(n, generator=g, device="cuda").to(torch.int32)}
+    res = {"n": n}
+    for name, idx in pats.items():
+        ms_c = timed(torch, lambda: vc.vc_gather_decode(c, w, idx, out), k, 2)
+        ms_f = timed(torch, lambda: vc.vcb_gather_f32(x, idx, out), k, 2)
+        res[name] = {"compressed_ms": ms_c, "float_ms": ms_f, "speedup": ms_f / ms_c,
+                     "compressed_gvecs": n / (ms_c * 1e-3) / 1e9}
+    del x, w, out, pats
+    return res
+
+
 BYTES_PER_VEC = {"axpy": 24, "dot": 16, "norm2": 8, "encode": 20}
 
 
@@ -412,6 +438,9 @@ def main():
         log("flux divergence (TGV Euler flux, 64^3 p=4 hexahedra)")
         extras["flux_div"] = bench_flux_div(torch, vc, inputs, k)
         log(f"flux divergence: {extras['flux_div']}")
+        log("indexed gather (2^26 vectors)")
+        extras["gather"] = bench_gather(torch, vc, k)
+        log(f"gather: {extras['gather']}")
         log("anisotropy error statistics (vMF, 2^25 vectors each)")
         extras["anisotropy"] = bench_anisotropy(torch, vc, inputs)
         log(f"anisotropy: " + ", ".join(f"{k}: {v['mean'][0]:.3e}" for k, v in extras["anisotropy"].items()

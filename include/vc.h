@@ -144,6 +144,20 @@ vc_status vc_fused_apply(const vc_codec* c, const float* M, int rows, int cols, 
 vc_status vc_flux_div_tp(const vc_codec* c, const float* d, int q, int np, const uint64_t* F, float* out,
                          size_t n_elem, hipStream_t stream);
 
+/* Random access to compressed vectors (fixed-rate codes are individually addressable, §1; the
+ * interface steps of flux reconstruction read neighbours' values through a connectivity array,
+ * Table fr_nse steps 2 and 8).
+ * vc_gather_decode : out[i] = decode(codes[idx[i]]) for i < n; codes has n_src entries, idx
+ *   (device uint32 [n]) entries >= n_src are not dereferenced and give (NaN, NaN, NaN); out is
+ *   float32 AoS [n][3] and must not overlap codes or idx.
+ * vc_scatter_encode: codes[idx[i]] = encode(xyz[i]) for i < n; idx entries >= n_dst are
+ *   skipped; with repeated indices the code written is one of the candidates, unspecified which.
+ * Single-precision decode; the encoder of the codec's precision. */
+vc_status vc_gather_decode(const vc_codec* c, const uint64_t* codes, size_t n_src, const uint32_t* idx, size_t n,
+                           float* out, hipStream_t stream);
+vc_status vc_scatter_encode(const vc_codec* c, const float* xyz, const uint32_t* idx, size_t n, uint64_t* codes,
+                            size_t n_dst, hipStream_t stream);
+
 /* ---- batched persistent launch over a segment table ---- */
 typedef enum { VC_OP_AXPY = 0, VC_OP_DOT = 1, VC_OP_NORM2 = 2, VC_OP_ENCODE = 3 } vc_op;
 

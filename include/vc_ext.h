@@ -74,6 +74,11 @@ vc_status vcx_error_hist(const vc_codec* c, const float* xyz, size_t n, const do
 vc_status vcb_flux_div_tp_f32(const float* d, int q, int np, const float* F, float* out, size_t n_elem,
                               hipStream_t stream);
 
+/* out[i] = src[idx[i]] for float32 AoS vectors (src [n_src][3]); indices >= n_src give NaN: the
+ * uncompressed twin of vc_gather_decode. */
+vc_status vcb_gather_f32(const float* src, size_t n_src, const uint32_t* idx, size_t n, float* out,
+                         hipStream_t stream);
+
 /* dst[0:bytes) = src[0:bytes): the attainable-bandwidth reference.  16-byte aligned. */
 vc_status vcb_copy(const void* src, void* dst, size_t bytes, hipStream_t stream);
 

@@ -73,6 +73,9 @@ _SIGS = {
     "vcx_batch_plan_info": ([_vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint32)], C.c_int),
     "vc_flux_div_tp": ([C.POINTER(vc_codec), _vp, C.c_int, C.c_int, _vp, _vp, C.c_size_t, _vp], C.c_int),
     "vcb_flux_div_tp_f32": ([_vp, C.c_int, C.c_int, _vp, _vp, C.c_size_t, _vp], C.c_int),
+    "vc_gather_decode": ([C.POINTER(vc_codec), _vp, C.c_size_t, _vp, C.c_size_t, _vp, _vp], C.c_int),
+    "vc_scatter_encode": ([C.POINTER(vc_codec), _vp, _vp, C.c_size_t, _vp, C.c_size_t, _vp], C.c_int),
+    "vcb_gather_f32": ([_vp, C.c_size_t, _vp, C.c_size_t, _vp, _vp], C.c_int),
     "vcx_error_hist": ([C.POINTER(vc_codec), _vp, C.c_size_t, _vp, C.c_int, _vp, _vp, _vp], C.c_int),
 }
 
@@ -259,6 +262,40 @@ def vcb_flux_div_tp_f32(d, F, out=None, stream=None):
         out = torch.empty((ne, ns, npq), dtype=torch.float32, device=F.device)
     _check(lib().vcb_flux_div_tp_f32(_ptr(d), q, npq, _ptr(F), _ptr(out), ne, _stream(stream)),
            "vcb_flux_div_tp_f32")
+    return out
+
+
+def vc_gather_decode(c: vc_codec, codes, idx, out=None, stream=None):
+    """out[i] = decode(codes[idx[i]]); codes int64 [n_src], idx int32 [n] (device)"""
+    torch = _torch()
+    _require(codes, torch.int64, "vc_gather_decode codes")
+    _require(idx, torch.int32, "vc_gather_decode idx")
+    n = idx.numel()
+    if out is None:
+        out = torch.empty((n, 3), dtype=torch.float32, device=idx.device)
+    _check(lib().vc_gather_decode(C.byref(c), _ptr(codes), codes.numel(), _ptr(idx), n, _ptr(out), _stream(stream)),
+           "vc_gather_decode")
+    return out
+
+
+def vc_scatter_encode(c: vc_codec, xyz, idx, codes, stream=None):
+    """codes[idx[i]] = encode(xyz[i])"""
+    torch = _torch()
+    _require(xyz, torch.float32, "vc_scatter_encode xyz")
+    _require(idx, torch.int32, "vc_scatter_encode idx")
+    _require(codes, torch.int64, "vc_scatter_encode codes")
+    _check(lib().vc_scatter_encode(C.byref(c), _ptr(xyz), _ptr(idx), idx.numel(), _ptr(codes), codes.numel(),
+                                   _stream(stream)), "vc_scatter_encode")
+    return codes
+
+
+def vcb_gather_f32(src, idx, out=None, stream=None):
+    torch = _torch()
+    n = idx.numel()
+    if out is None:
+        out = torch.empty((n, 3), dtype=torch.float32, device=idx.device)
+    _check(lib().vcb_gather_f32(_ptr(src), src.numel() // 3, _ptr(idx), n, _ptr(out), _stream(stream)),
+           "vcb_gather_f32")
     return out
 
 

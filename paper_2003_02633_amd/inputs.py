@@ -156,6 +156,28 @@ def vmf_torch(n: int, kappa: float, mean=(0.0, 0.0, 1.0), seed: int = 0, sigma: 
     return (d * r).to(torch.float32).contiguous()
 
 
+def sampler_torch(kind: str, n: int, seed: int, device="cuda", radius: float = 1.0):
+    """GPU-side draws (torch's seeded Philox) of the unit-ball samplers: ``sphere`` (uniform on
+    S^2: normalised FP64 Gaussians), ``cube`` (uniform in [-1, 1]^3) and ``angles`` (theta, phi
+    uniform on [-pi, pi) x [0, pi)), scaled by ``radius``, rounded to FP32 [n, 3]."""
+    import torch
+
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    if kind == "sphere":
+        d = torch.randn((n, 3), generator=g, dtype=torch.float64, device=device)
+        v = d / torch.linalg.vector_norm(d, dim=1, keepdim=True).clamp_min(1e-300)
+    elif kind == "cube":
+        v = 2.0 * torch.rand((n, 3), generator=g, dtype=torch.float64, device=device) - 1.0
+    elif kind == "angles":
+        th = (2.0 * torch.rand(n, generator=g, dtype=torch.float64, device=device) - 1.0) * math.pi
+        ph = torch.rand(n, generator=g, dtype=torch.float64, device=device) * math.pi
+        v = torch.stack([torch.cos(th) * torch.sin(ph), torch.sin(th) * torch.sin(ph), torch.cos(ph)], dim=1)
+    else:
+        raise ValueError(kind)
+    return (radius * v).to(torch.float32).contiguous()
+
+
 def gauss_legendre_nodes(k: int) -> np.ndarray:
     x, _ = np.polynomial.legendre.leggauss(k)
     return x

@@ -196,3 +196,15 @@ def test_flux_div_validation_without_device_work(lib):
     assert lib.vc_flux_div_tp(P, None, 5, 5, f(0x20000), f(0x80000000), 4, None) == 1
     assert lib.vc_flux_div_tp(P, None, 5, 5, None, None, 0, None) == 0
     assert lib.vcb_flux_div_tp_f32(f(0x10000), 5, 5, f(0x20002), f(0x80000000), 4, None) == 2
+
+
+def test_gather_scatter_validation_without_device_work(lib):
+    P = C.byref(vc.codec())
+    f = _fake
+    assert lib.vc_gather_decode(P, f(0x10000), 16, f(0x20000), 8, None, None) == 1
+    assert lib.vc_gather_decode(P, f(0x10004), 16, f(0x20000), 8, f(0x80000000), None) == 2
+    assert lib.vc_gather_decode(P, f(0x10000), 16, f(0x20000), 8, f(0x10000 + 8), None) == 7
+    assert lib.vc_gather_decode(P, None, 0, None, 0, None, None) == 0
+    assert lib.vc_scatter_encode(P, f(0x10000), f(0x20002), 8, f(0x30000), 8, None) == 2
+    assert lib.vc_scatter_encode(P, f(0x10000), f(0x20000), 8, f(0x10000 + 16), 8, None) == 7
+    assert lib.vcb_gather_f32(f(0x10000), 16, None, 8, f(0x30000), None) == 1

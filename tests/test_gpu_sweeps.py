@@ -1,0 +1,68 @@
+"""The GPU error pipeline (library encoder + FP64 error norms) against numbers the paper prints
+(tests/golden/paper_numbers.txt), at 2^24 samples per point."""
+import math
+import sys
+
+import pytest
+
+import paper_2003_02633_amd as vc
+from paper_2003_02633_amd import sweeps
+
+pytestmark = pytest.mark.gpu
+
+N = 1 << 24
+
+
+def say(m):
+    print(m, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    assert torch.cuda.is_available(), "GPU test without a GPU"
+    return vc.lib()
+
+
+def _within(r, ref, k=4.0, floor=0.0):
+    sem = r["sigma"] / math.sqrt(r["n"])
+    return abs(r["mean"] - ref) < k * sem + floor
+
+
+def test_table_cpp_error_on_gpu(lib, paper):
+    """§3 Table (C++_error), double/double rows: mean on S^2 and in [-1,1]^3, max on S^2"""
+    s = sweeps.stats(vc, vc.codec(), "sphere", N, 21)
+    cb = sweeps.stats(vc, vc.codec(), "cube", N, 22)
+    say(f"sphere {s}; cube {cb}")
+    assert _within(s, paper["dd_sphere_mean"], floor=5e-10)
+    assert _within(cb, paper["dd_cube_mean"], floor=5e-10)
+    assert 0.99 * paper["dd_sphere_max"] < s["max"] <= 1.02 * paper["dd_sphere_max"]
+
+
+def test_section23_layout_averages_on_gpu(lib, paper):
+    """§2.3 averages of three layouts (reading: angle-uniform sampling), within 0.5 %"""
+    for lay, key in (("0,8,23-16-17", "avg_0_8_23_16_17"), ("0,7,23-17-17", "avg_0_7_23_17_17"),
+                     ("0,7,22-17-18", "avg_0_7_22_17_18")):
+        r = sweeps.stats(vc, vc.codec(lay), "angles", N, 23)
+        say(f"{lay}: {r['mean']:.5e} vs {paper[key]:.3e}")
+        assert abs(r["mean"] / paper[key] - 1) < 0.005
+
+
+def test_frac_sweep_in_figure_ranges(lib, paper):
+    """§2.4 Fig. (frac_1718): mean and sigma stay inside the plotted axes for P in [2^16, 2^18];
+    P = 2^17 equals the plain codec"""
+    for P in (1 << 16, 92682, 1 << 17, 163840, 1 << 18):
+        r = sweeps.stats(vc, vc.codec(mode="frac", P=P), "sphere", 1 << 22, 24)
+        say(f"P={P}: mean {r['mean']:.4e} sigma {r['sigma']:.4e}")
+        assert paper["frac_mean_lo"] < r["mean"] < paper["frac_mean_hi"]
+        assert paper["frac_sigma_lo"] < r["sigma"] < paper["frac_sigma_hi"]
+
+
+def test_tanh_sigma_reduction_on_gpu(lib, paper):
+    """§2.5: tanh companding with gamma = 0.5 lowers sigma(e) by about 2 %"""
+    base = sweeps.stats(vc, vc.codec(), "sphere", N, 25)
+    t = sweeps.stats(vc, vc.codec(mode="tanh", gamma=0.5), "sphere", N, 25)
+    red = 1 - t["sigma"] / base["sigma"]
+    say(f"sigma reduction {red:.4f}")
+    assert abs(red - paper["tanh_sigma_reduction"]) < 0.01
