@@ -309,7 +309,8 @@ def main():
     ap.add_argument("--n", type=int, default=1 << 27)
     ap.add_argument("--quick", action="store_true", help="skip the side-by-side extras")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--pmc-run", action="store_true", help="one copy + one axpy launch (profiling)")
+    ap.add_argument("--pmc-run", nargs="?", const="axpy", default=None, choices=["axpy", "apply", "fdiv", "all"],
+                    help="launch the profiled kernels once (copy + axpy by default) for rocprofv3 --pmc")
     ap.add_argument("--precision", default="f64", choices=["f64", "f32"],
                     help="encoder arithmetic of the headline codec")
     args = ap.parse_args()
@@ -339,14 +340,23 @@ def main():
     torch.cuda.synchronize()
 
     if args.pmc_run:
-        cp_src = torch.empty(N * 3, dtype=torch.float32, device=dev)
-        cp_src.copy_(a32.view(-1))
-        cp_dst = torch.empty_like(cp_src)
-        vc.vcb_copy(cp_src, cp_dst)
+        # one launch of each profiled kernel: copy (calibration) and axpy, or the fused apply,
+        # or the flux divergence (compressed and float32)
+        if args.pmc_run in ("axpy", "all"):
+            cp_src = torch.empty(N * 3, dtype=torch.float32, device=dev)
+            cp_src.copy_(a32.view(-1))
+            cp_dst = torch.empty_like(cp_src)
+            vc.vcb_copy(cp_src, cp_dst)
+            torch.cuda.synchronize()
+            vc.vc_axpy(c, ALPHA, wa, wb, wc)
+            torch.cuda.synchronize()
+            del cp_src, cp_dst
+        if args.pmc_run in ("apply", "all"):
+            bench_apply(torch, vc, inputs, 1)
+        if args.pmc_run in ("fdiv", "all"):
+            bench_flux_div(torch, vc, inputs, 1)
         torch.cuda.synchronize()
-        vc.vc_axpy(c, ALPHA, wa, wb, wc)
-        torch.cuda.synchronize()
-        print(json.dumps({"pmc_run": True, "n_vectors": N, "copy_bytes_each_way": N * 12,
+        print(json.dumps({"pmc_run": args.pmc_run, "n_vectors": N, "copy_bytes_each_way": N * 12,
                           "kernel_hash": kernel_hash()}), flush=True)
         return
 
