@@ -9,16 +9,20 @@
 //   div_kp = sum_a d_0[a][kx] X_(a,ky,kz)p.x + sum_a d_1[a][ky] X_(kx,a,kz)p.y
 //          + sum_a d_2[a][kz] X_(kx,ky,a)p.z.
 //
-// A workgroup takes EPW elements and makes three passes, one thread per line of q points:
-//   x: load the line's q codes (all in flight at once), decode each once, apply d_0 into an LDS
-//      accumulator and keep the y and z components in LDS;
-//   y: add d_1 along the y lines;
-//   z: add d_2 along the z lines and store -- for a z line, consecutive lanes (equation, then x,
-//      then y) hold consecutive outputs, so the stores are coalesced.
+// A persistent workgroup takes groups of EPW elements in turn.  For each group it
+//   stages: the group's rows are contiguous, so consecutive lanes load consecutive codes; each
+//      code is decoded once into LDS.  The loads of the workgroup's next group are issued right
+//      after, into the same registers, and stay in flight through the three passes below;
+//   x: one thread per x line of q points applies d_0 into an LDS accumulator;
+//   y: adds d_1 along the y lines;
+//   z: adds d_2 along the z lines and stores -- for a z line, consecutive lanes (equation, then
+//      x, then y) hold consecutive outputs, so the stores are coalesced.
 // The derivative coefficients are uniform across threads.  The same kernel reads plain float32
 // fluxes as the uncompressed baseline.
 #include "vc_internal.hpp"
 #include "../../include/vc_ext.h"
+
+#include <type_traits>
 
 namespace vc {
 
@@ -31,140 +35,149 @@ __global__ __launch_bounds__(FD_BS) void k_fdiv_tp(const float* __restrict__ d, 
                                                    size_t n_elem, int EPW, Params P)
 {
   constexpr int Q2 = Q * Q, Q3 = Q * Q * Q;
+  // EPW = FD_BS / (Q^2 NP) elements per group when that is >= 1: at most FD_BS lines and FD_BS Q
+  // rows.  Only Q = 6 with NP = 8 (288 lines) falls back to one element and a loop over lines.
+  constexpr bool MULTI = Q * Q * 8 > FD_BS;
+  constexpr int ROWS_MAX = MULTI ? Q * Q * Q * 8 : FD_BS * Q;
+  constexpr int RPT = (CODES ? 1 : 3) * ((ROWS_MAX + FD_BS - 1) / FD_BS);   // staged loads per thread
   extern __shared__ float sm[];
-  const int per = Q3 * NP;                    // flux rows (= outputs) per element
-  float* Ys = sm;                             // [EPW][Q3][NP] y components
-  float* Zs = sm + (size_t)EPW * per;         // [EPW][Q3][NP] z components
-  float* Os = sm + (size_t)2 * EPW * per;     // [EPW][Q3][NP] accumulator
-  // the 3 q x q derivative coefficients, staged once; each pass reads its own q x q block with
-  // uniform (broadcast) LDS reads right before use, so only q^2 of them are live at a time
-  __shared__ float dsh[3 * Q2];
-  for (int i = threadIdx.x; i < 3 * Q2; i += FD_BS) dsh[i] = d[i];
-  __syncthreads();
+  const int per = Q3 * NP;
+  const int gsz = EPW * per;
+  float* V = sm;                              // [EPW][Q3][NP][3] decoded flux vectors
+  float* Os = sm + 3 * gsz;                   // [EPW][Q3][NP] accumulator
   // Lines l = ((e Q + u) Q + v) NP + p, (u, v) the two coordinates that stay fixed along the
   // line; rows of line position a: x (a, v, u) = rx + a NP, y (v, a, u) = ry + a Q NP,
   // z (v, u, a) = rz + a Q^2 NP.
   auto bases = [&](int l, int& rx, int& ry, int& rz) {
-    const int t = (int)(((uint32_t)l * np_rcp) >> 20);   // l / NP, exact for l < 2^20 / NP
+    const int t = (int)(((uint32_t)l * np_rcp) >> 20);
     const int p = l - t * NP;
     const int v = t % Q, u = (t / Q) % Q, e = t / Q2;
     rx = (e * Q3 + Q * v + Q2 * u) * NP + p;
     ry = (e * Q3 + v + Q2 * u) * NP + p;
     rz = (e * Q3 + v + Q * u) * NP + p;
   };
-  // a thread's first line (l = threadIdx.x) is the same in every group: its bases are computed once
-  int rx0, ry0, rz0;
+  int rx0, ry0, rz0;                          // a thread's first line is the same in every group
   bases(threadIdx.x, rx0, ry0, rz0);
-
+  auto for_lines = [&](int nlines, auto&& fn) {
+    if constexpr (!MULTI) {
+      if ((int)threadIdx.x < nlines) fn(rx0, ry0, rz0);
+    } else {
+      for (int l = threadIdx.x; l < nlines; l += FD_BS) {
+        int rx, ry, rz;
+        bases(l, rx, ry, rz);
+        fn(rx, ry, rz);
+      }
+    }
+  };
+  // The q x q coefficients of one direction, read with scalar loads right before its pass.  The
+  // empty asm hides the pointer's value from the optimiser, which would otherwise hoist all
+  // 3 q^2 loads out of the group loop and spill them; the constant address space keeps the
+  // reads scalar.
+  auto coeffs = [&](int c, float (&dc)[Q][Q]) {
+    const float* dp = d + c * Q2;
+    asm volatile("" : "+s"(dp));
+    typedef const __attribute__((address_space(4))) float cfloat;
+    cfloat* cp = (cfloat*)dp;
+#pragma unroll
+    for (int a = 0; a < Q; a++)
+#pragma unroll
+      for (int b = 0; b < Q; b++) dc[a][b] = cp[a * Q + b];
+  };
   const size_t ngroups = (n_elem + EPW - 1) / EPW;
-  for (size_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
+  using R_t = typename std::conditional<CODES, uint64_t, float>::type;
+  R_t r[RPT];                                 // the staged rows of the next group
+  auto load = [&](size_t g) {
+    const size_t e0 = g * (size_t)EPW;
+    const int ne = (int)((n_elem - e0) < (size_t)EPW ? (n_elem - e0) : (size_t)EPW);
+    const int cnt = CODES ? ne * per : 3 * ne * per;
+    const R_t* src = (const R_t*)Fv + e0 * per * (CODES ? 1 : 3);
+#pragma unroll
+    for (int i = 0; i < RPT; i++) {
+      const int k = (int)threadIdx.x + i * FD_BS;
+      if (k < cnt) r[i] = __builtin_nontemporal_load(src + k);
+    }
+  };
+  size_t g = blockIdx.x;
+  if (g < ngroups) load(g);
+  for (; g < ngroups; g += gridDim.x) {
     const size_t e0 = g * (size_t)EPW;
     const int ne = (int)((n_elem - e0) < (size_t)EPW ? (n_elem - e0) : (size_t)EPW);
     const int nlines = ne * Q2 * NP;
-    const uint64_t* Fc = (const uint64_t*)Fv + e0 * per;    // this group's rows (uniform base)
-    const float* Ff = (const float*)Fv + e0 * per * 3;
     float* og = out + e0 * per;
-
-    // ---- x: load and decode a line of q rows, apply d_0, keep y and z for the other passes
+    // ---- stage: decode this group's rows into LDS, then start loading the next group, whose
+    //      loads stay in flight through the three passes
     {
-      float dx[Q][Q];   // this pass's coefficients (uniform LDS reads)
+      const int cnt = CODES ? ne * per : 3 * ne * per;
 #pragma unroll
-      for (int a = 0; a < Q; a++)
-#pragma unroll
-        for (int b = 0; b < Q; b++) dx[a][b] = dsh[a * Q + b];
-      auto xline = [&](int r0) {
-        float fx[Q];
-        if constexpr (CODES) {
-          uint64_t w[Q];
-#pragma unroll
-          for (int a = 0; a < Q; a++)
-            w[a] = __builtin_nontemporal_load((const uint64_t*)((const char*)Fc + (uint32_t)(r0 + a * NP) * 8u));
-#pragma unroll
-          for (int a = 0; a < Q; a++) {
-            float y, z;
-            decode_vec<L, MODE>(w[a], P, fx[a], y, z);
-            Ys[r0 + a * NP] = y;
-            Zs[r0 + a * NP] = z;
+      for (int i = 0; i < RPT; i++) {
+        const int k = (int)threadIdx.x + i * FD_BS;
+        if (k < cnt) {
+          if constexpr (CODES) {
+            float x, y, z;
+            decode_vec<L, MODE>(r[i], P, x, y, z);
+            V[3 * k] = x; V[3 * k + 1] = y; V[3 * k + 2] = z;
+          } else {
+            V[k] = r[i];
           }
-        } else {
-          float y[Q], z[Q];
-#pragma unroll
-          for (int a = 0; a < Q; a++) {
-            const float* f = (const float*)((const char*)Ff + (uint32_t)(r0 + a * NP) * 12u);
-            fx[a] = __builtin_nontemporal_load(f);
-            y[a] = __builtin_nontemporal_load(f + 1);
-            z[a] = __builtin_nontemporal_load(f + 2);
-          }
-#pragma unroll
-          for (int a = 0; a < Q; a++) { Ys[r0 + a * NP] = y[a]; Zs[r0 + a * NP] = z[a]; }
         }
+      }
+    }
+    if (g + gridDim.x < ngroups) load(g + gridDim.x);
+    __syncthreads();
+    // ---- x: apply d_0 along the x lines into the accumulator
+    {
+      float dc[Q][Q];
+      coeffs(0, dc);
+      for_lines(nlines, [&](int rx, int, int) {
+        float f[Q];
+#pragma unroll
+        for (int a = 0; a < Q; a++) f[a] = V[3 * (rx + a * NP)];
 #pragma unroll
         for (int b = 0; b < Q; b++) {
           float s = 0.0f;
 #pragma unroll
-          for (int a = 0; a < Q; a++) s = __builtin_fmaf(dx[a][b], fx[a], s);
-          Os[r0 + b * NP] = s;
+          for (int a = 0; a < Q; a++) s = __builtin_fmaf(dc[a][b], f[a], s);
+          Os[rx + b * NP] = s;
         }
-      };
-      for (int l = threadIdx.x; l < nlines; l += FD_BS) {
-        int rx = rx0, ry = ry0, rz = rz0;
-        if (l != (int)threadIdx.x) bases(l, rx, ry, rz);
-        xline(rx);
-      }
+      });
     }
     __syncthreads();
     // ---- y: add d_1 along the y lines
     {
-      float dy[Q][Q];
-#pragma unroll
-      for (int a = 0; a < Q; a++)
-#pragma unroll
-        for (int b = 0; b < Q; b++) dy[a][b] = dsh[Q2 + a * Q + b];
-      auto yline = [&](int r0) {
+      float dc[Q][Q];
+      coeffs(1, dc);
+      for_lines(nlines, [&](int, int ry, int) {
         float f[Q];
 #pragma unroll
-        for (int a = 0; a < Q; a++) f[a] = Ys[r0 + a * Q * NP];
+        for (int a = 0; a < Q; a++) f[a] = V[3 * (ry + a * Q * NP) + 1];
 #pragma unroll
         for (int b = 0; b < Q; b++) {
           float s = 0.0f;
 #pragma unroll
-          for (int a = 0; a < Q; a++) s = __builtin_fmaf(dy[a][b], f[a], s);
-          Os[r0 + b * Q * NP] += s;
+          for (int a = 0; a < Q; a++) s = __builtin_fmaf(dc[a][b], f[a], s);
+          Os[ry + b * Q * NP] += s;
         }
-      };
-      for (int l = threadIdx.x; l < nlines; l += FD_BS) {
-        int rx = rx0, ry = ry0, rz = rz0;
-        if (l != (int)threadIdx.x) bases(l, rx, ry, rz);
-        yline(ry);
-      }
+      });
     }
     __syncthreads();
     // ---- z: add d_2 along the z lines and store (consecutive lanes write consecutive outputs)
     {
-      float dz[Q][Q];
-#pragma unroll
-      for (int a = 0; a < Q; a++)
-#pragma unroll
-        for (int b = 0; b < Q; b++) dz[a][b] = dsh[2 * Q2 + a * Q + b];
-      auto zline = [&](int r0) {
+      float dc[Q][Q];
+      coeffs(2, dc);
+      for_lines(nlines, [&](int, int, int rz) {
         float f[Q];
 #pragma unroll
-        for (int a = 0; a < Q; a++) f[a] = Zs[r0 + a * Q2 * NP];
+        for (int a = 0; a < Q; a++) f[a] = V[3 * (rz + a * Q2 * NP) + 2];
 #pragma unroll
         for (int b = 0; b < Q; b++) {
-          float s = Os[r0 + b * Q2 * NP];
+          float s = Os[rz + b * Q2 * NP];
 #pragma unroll
-          for (int a = 0; a < Q; a++) s = __builtin_fmaf(dz[a][b], f[a], s);
-          __builtin_nontemporal_store(s, (float*)((char*)og + (uint32_t)(r0 + b * Q2 * NP) * 4u));
+          for (int a = 0; a < Q; a++) s = __builtin_fmaf(dc[a][b], f[a], s);
+          __builtin_nontemporal_store(s, (float*)((char*)og + (uint32_t)(rz + b * Q2 * NP) * 4u));
         }
-      };
-      for (int l = threadIdx.x; l < nlines; l += FD_BS) {
-        int rx = rx0, ry = ry0, rz = rz0;
-        if (l != (int)threadIdx.x) bases(l, rx, ry, rz);
-        zline(rz);
-      }
+      });
     }
-    __syncthreads();   // Ys / Zs / Os are reused by the next group
+    __syncthreads();   // V and Os are reused by the next group
   }
 }
 
@@ -175,7 +188,7 @@ static inline int fdiv_epw(int q, int np)
   return e < 1 ? 1 : e;
 }
 
-static inline size_t fdiv_lds(int q, int np) { return (size_t)3 * fdiv_epw(q, np) * q * q * q * np * sizeof(float); }
+static inline size_t fdiv_lds(int q, int np) { return (size_t)4 * fdiv_epw(q, np) * q * q * q * np * sizeof(float); }
 
 template <class L, int MODE, int Q, bool CODES>
 static vc_status fdiv_q(const Resolved& R, const float* d, int np, const void* F, float* out, size_t n_elem,
