@@ -156,19 +156,30 @@ enum Prec { PREC_F32 = 0, PREC_F64 = 1 };
 
 // ------------------------------------------------------------------ decode
 
+// Magnitude r_hat = (1 + M/2^m) 2^(E - b) of a code, an exact float32 bit pattern (§2.3); zero for
+// E = 0 (IEEE subnormals for the layouts that keep them), NaN for the reserved all-ones exponent.
+// The E and M fields are adjacent in the high word (E above M), so one shift and mask place them
+// as the float's exponent and leading mantissa bits.
+template <class L>
+VC_DI float decode_mag(uint64_t w)
+{
+  static_assert(L::sh_m >= 32, "E and M fields in the high word");
+  const uint32_t hi = (uint32_t)(w >> 32);
+  const uint32_t em = (hi >> (L::sh_m - 32)) & ((1u << (L::e + L::m)) - 1u);
+  const uint32_t rbits = L::keep_sub ? em << (23 - L::m)                       // the IEEE value itself
+                                     : (em << (23 - L::m)) + ((uint32_t)(127 - L::bias) << 23);
+  float r = ubits(rbits);
+  const uint32_t Eb = hi & (L::emask << (L::sh_e - 32));                   // E in place
+  if (!L::keep_sub && Eb == 0u) r = 0.0f;
+  if (Eb == (L::emask << (L::sh_e - 32))) r = ubits(0x7fc00000u);          // reserved -> NaN
+  return r;
+}
+
 // Cartesian vector of a code: Eq. (a_inv) then Eq. (cart2sphere).
 template <class L, int MODE>
 VC_DI void decode_vec(uint64_t w, const Params& P, float& ox, float& oy, float& oz)
 {
-  const uint32_t E = (uint32_t)(w >> L::sh_e) & L::emask;
-  const uint32_t M = (uint32_t)(w >> L::sh_m) & ((1u << L::m) - 1u);
-  // magnitude (1 + M/2^m) 2^(E - b): an exact float32 bit pattern
-  uint32_t rbits;
-  if (L::keep_sub) rbits = (E << 23) | (M << (23 - L::m));                 // the IEEE value itself
-  else rbits = ((E + (uint32_t)(127 - L::bias)) << 23) | (M << (23 - L::m));
-  float r = ubits(rbits);
-  if (!L::keep_sub && E == 0) r = 0.0f;
-  if (E == L::emask) r = ubits(0x7fc00000u);                               // reserved -> NaN
+  float r = decode_mag<L>(w);
 
   uint32_t nth, nph;
   if (MODE == FRAC) {
@@ -216,21 +227,6 @@ VC_DI void decode_vec(uint64_t w, const Params& P, float& ox, float& oy, float& 
   ox = rs * ct;
   oy = rs * st;
   oz = r * cp;
-}
-
-// magnitude r_hat = |decode(w)| from the fields alone
-template <class L>
-VC_DI float decode_mag(uint64_t w)
-{
-  const uint32_t E = (uint32_t)(w >> L::sh_e) & L::emask;
-  const uint32_t M = (uint32_t)(w >> L::sh_m) & ((1u << L::m) - 1u);
-  uint32_t rbits;
-  if (L::keep_sub) rbits = (E << 23) | (M << (23 - L::m));
-  else rbits = ((E + (uint32_t)(127 - L::bias)) << 23) | (M << (23 - L::m));
-  float r = ubits(rbits);
-  if (!L::keep_sub && E == 0) r = 0.0f;
-  if (E == L::emask) r = ubits(0x7fc00000u);
-  return r;
 }
 
 // ------------------------------------------------------------------ encode helpers
@@ -549,8 +545,8 @@ VC_DI uint64_t encode_vec32(float x, float y, float z, const Params& P)
 // reciprocal/rsqrt are ~2^-24 accurate and get one correction step each.
 
 // Level coordinate of atan2(num, den), num, den >= 0: V = Kq atan2/(pi/2) (den >= 0),
-// 2 Kq - that (den < 0), with C = Kq/(pi/2).
-VC_DI double angle_levels64(double num, double den, bool den_neg, double Kq_half, double C)
+// 2 Kq - that (den < 0), with C = Kq/(pi/2), plus `add` (a multiple of 1/2).
+VC_DI double angle_levels64(double num, double den, bool den_neg, double Kq_half, double C, double add = 0.0)
 {
   constexpr double T8 = 0.41421356237309503;      // tan(pi/8)
   const bool swap = num > den;
@@ -569,11 +565,14 @@ VC_DI double angle_levels64(double num, double den, bool den_neg, double Kq_half
 #pragma unroll
   for (int i = VC_ATAN_R64_DEG - 1; i >= 0; i--) Rp = fma64_(Rp, s2, VC_ATAN_R64[i]);
   const double at = fma64_(b, s2 * Rp, b);        // atan(b)
-  // octant offset in units of Kq/2: atan2 = [swap] pi/2 +- ([R] pi/4 + atan b), mirrored for den < 0
+  // octant: atan2 = k pi/4 + sgn atan(b) with k = k0 + sgn [R], k0 = 2 if swapped, else 4 if
+  // den < 0, else 0, and sgn = -1 when exactly one of (den < 0, swapped) holds; all in doubles
+  // (k, k Kq_half + add and sgn atan(b) are exact)
   const bool neg = den_neg != swap;
-  const int k0 = swap ? 2 : (den_neg ? 4 : 0);
-  const int k = neg ? k0 - (int)R : k0 + (int)R;
-  return fma64_(C, neg ? -at : at, (double)k * Kq_half);
+  const double sgn = neg ? -1.0 : 1.0;
+  const double k0 = swap ? 2.0 : (den_neg ? 4.0 : 0.0);
+  const double k = fma64_(sgn, Rd, k0);
+  return fma64_(C, sgn * at, fma64_(k, Kq_half, add));
 }
 
 // Companded level distance from the centre: K h(q/K) for q = K |u| >= 0.
@@ -606,13 +605,14 @@ VC_DI double compand64(double q, double invK, const Params& P)
 template <class L, int MODE>
 VC_DI uint64_t encode_vec64(float x, float y, float z, const Params& P)
 {
-  const uint32_t ax = fbits(x) & 0x7fffffffu, ay = fbits(y) & 0x7fffffffu, az = fbits(z) & 0x7fffffffu;
-  const uint32_t amax = umax3(ax, ay, az);
-  if (amax >= 0x7f800000u) return L::reserved;    // non-finite input
-  if (amax == 0u) return 0ull;                    // zero vector
-  const double X = (double)x, Y = (double)y, Z = (double)z;   // exact; squares exact in FP64
+  // |x|, |y|, |z| (the signs are taken from the inputs below); exact, and squares exact in FP64
+  const double X = (double)__builtin_fabsf(x), Y = (double)__builtin_fabsf(y), Z = (double)__builtin_fabsf(z);
   const double R2 = fma64_(X, X, Y * Y);          // rho^2, one rounding
   const double S = fma64_(Z, Z, R2);              // r^2, two roundings (2^-52)
+  // a finite float squares to below 2^256, so S is finite exactly when every component is; the
+  // squares of nonzero floats are normal doubles, so S is zero only for the zero vector
+  if (!(S < __builtin_huge_val())) return L::reserved;   // non-finite input
+  if (S == 0.0) return 0ull;                      // zero vector
 
   // ---- magnitude: r to ~2^-47 (rsqrt seed + one Newton step), nearest-even at 1+m bits
   const double yS = rsq64_(S);
@@ -658,7 +658,7 @@ VC_DI uint64_t encode_vec64(float x, float y, float z, const Params& P)
 
   // ---- theta: |Q| = Kt |theta|/pi; n = base + floor(+-|Q| (+1/2 if n_theta_max is even))
   const bool yneg = y < 0.0f, xneg = x < 0.0f, zneg = z < 0.0f;
-  double Q = angle_levels64(__builtin_fabs(Y), __builtin_fabs(X), xneg, 0.25 * P.Kt64, P.Ct64);
+  double Q = angle_levels64(Y, X, xneg, 0.25 * P.Kt64, P.Ct64);
   if ((MODE == TANH || MODE == COS) && P.comp_t) Q = compand64<MODE>(Q, P.invKt64, P);
   uint32_t nth;
   if (MODE == FRAC) {
@@ -673,18 +673,22 @@ VC_DI uint64_t encode_vec64(float x, float y, float z, const Params& P)
   if (R2 == 0.0) nth = P.base_t;                  // pole: theta = atan2(0, 0) = 0
 
   // ---- phi: V = n_phi_max phi/pi; n = floor(V + 1/2)
-  const double V = angle_levels64(rho, __builtin_fabs(Z), zneg, 0.25 * P.Np64, P.Cp64);
   uint32_t nph;
   if ((MODE == TANH || MODE == COS) && P.comp_p) {
+    const double V = angle_levels64(rho, Z, zneg, 0.25 * P.Np64, P.Cp64);
     const double Qc = V - 0.5 * P.Np64;           // (n_phi_max/2) u_phi, exact zero at phi = pi/2
     const double m = compand64<MODE>(__builtin_fabs(Qc), P.invKc64, P);
     nph = (uint32_t)((int)((P.nmax_p + 1u) / 2u) + (int)floor64_(Qc < 0 ? -m : m));
   } else {
-    nph = (uint32_t)(int)(V + 0.5);               // V >= 0: truncation is the floor
+    const double Vh = angle_levels64(rho, Z, zneg, 0.25 * P.Np64, P.Cp64, 0.5);   // V + 1/2
+    nph = (uint32_t)(int)Vh;                      // Vh >= 0: truncation is the floor
   }
 
   if (MODE == FRAC) return em | ((uint64_t)nph * (uint64_t)P.T + (uint64_t)nth);
-  return ((uint64_t)nph << L::t) + (em | (uint64_t)nth);
+  // the E and M fields lie in the high word; n_phi straddles the two words
+  const uint32_t lo = nth | (nph << L::t);
+  const uint32_t hi = (uint32_t)(em >> 32) | (nph >> (32 - L::t));
+  return ((uint64_t)hi << 32) | lo;
 }
 
 // precision dispatch
