@@ -85,10 +85,29 @@ def read_valu(n: int):
         return None
 
 
-def timed(torch, fn, steps: int, warmup: int) -> float:
-    """Average milliseconds per call of fn() (all work on torch's current stream)."""
-    for _ in range(warmup):
+# Side-by-side timings warm up by time, not count: the clocks drop within milliseconds of idle
+# (host-side set-up between measurements) and take about 20 ms of load to come back up.
+WX = None
+SETTLE_MS = 25.0
+
+
+def timed(torch, fn, steps: int, warmup) -> float:
+    """Average milliseconds per call of fn() (all work on torch's current stream), after `warmup`
+    untimed calls, or (warmup None) untimed calls for at least SETTLE_MS."""
+    import time
+
+    if warmup is None:
+        # one call to size the rest, then enough back-to-back calls to fill SETTLE_MS
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         fn()
+        torch.cuda.synchronize()
+        t1 = max((time.perf_counter() - t0) * 1e3, 1e-3)
+        for _ in range(min(10000, int(SETTLE_MS / t1) + 1)):
+            fn()
+    else:
+        for _ in range(warmup):
+            fn()
     torch.cuda.synchronize()
     s = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -171,7 +190,7 @@ def bench_apply(torch, vc, inputs, k: int):
     del vel
     M = torch.from_numpy(inputs.uniform_matrix(rows, cols, 2)).to("cuda")
     out = torch.empty((E, rows, 3), dtype=torch.float32, device="cuda")
-    ms = timed(torch, lambda: vc.vc_fused_apply(c, M, U.view(E, cols), out), k, 2)
+    ms = timed(torch, lambda: vc.vc_fused_apply(c, M, U.view(E, cols), out), k, WX)
     flop = 2.0 * rows * cols * 3 * E
     byts = 8.0 * cols * E + 12.0 * rows * E
     del U, M, out
@@ -230,8 +249,8 @@ def bench_flux_div(torch, vc, inputs, k: int, grid=(64, 64, 64), p: int = 4):
     # with nothing else, but single short timings of either vary by a few per cent)
     mc, mu = [], []
     for _ in range(5):
-        mc.append(timed(torch, lambda: vc.vc_flux_div_tp(c, d, W, out), k, 2))
-        mu.append(timed(torch, lambda: vc.vcb_flux_div_tp_f32(d, F, out), k, 2))
+        mc.append(timed(torch, lambda: vc.vc_flux_div_tp(c, d, W, out), k, WX))
+        mu.append(timed(torch, lambda: vc.vcb_flux_div_tp_f32(d, F, out), k, WX))
     ms_c, ms_u = float(np.median(mc)), float(np.median(mu))
     bc, bu = 7500.0 * n, 10000.0 * n
     del F, W, out
@@ -258,8 +277,8 @@ def bench_gather(torch, vc, k: int, n: int = 1 << 26):
             "random": torch.randperm(n, generator=g, device="cuda").to(torch.int32)}
     res = {"n": n}
     for name, idx in pats.items():
-        ms_c = timed(torch, lambda: vc.vc_gather_decode(c, w, idx, out), k, 2)
-        ms_f = timed(torch, lambda: vc.vcb_gather_f32(x, idx, out), k, 2)
+        ms_c = timed(torch, lambda: vc.vc_gather_decode(c, w, idx, out), k, WX)
+        ms_f = timed(torch, lambda: vc.vcb_gather_f32(x, idx, out), k, WX)
         res[name] = {"compressed_ms": ms_c, "float_ms": ms_f, "speedup": ms_f / ms_c,
                      "compressed_gvecs": n / (ms_c * 1e-3) / 1e9}
     del x, w, out, pats
@@ -299,7 +318,7 @@ def bench_batch(torch, vc, inputs, k: int, precision: str):
            "algorithmic_bytes": algo}
     for name, fn in (("persistent_graph", plan.run), ("separate_launches", plan.run_separate),
                      ("separate_launches_graph", plan.run_separate_graph)):
-        ms = timed(torch, fn, k, 2)
+        ms = timed(torch, fn, k, WX)
         res[name] = {"ms": ms, "GBs": algo / (ms * 1e-3) / 1e9}
     plan.close()
     del segs
@@ -310,7 +329,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=25,
+                    help="untimed launches first; the clocks take about 20 ms of load to settle")
     ap.add_argument("--n", type=int, default=1 << 27)
     ap.add_argument("--quick", action="store_true", help="skip the side-by-side extras")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -383,7 +403,7 @@ def main():
         k = max(3, args.steps // 4)
         # uncompressed FP32 axpy over the same vectors (36 B/vec)
         c32 = torch.empty_like(a32)
-        ms_f32 = timed(torch, lambda: vc.vcb_axpy_f32(ALPHA, a32, b32, c32), k, 2)
+        ms_f32 = timed(torch, lambda: vc.vcb_axpy_f32(ALPHA, a32, b32, c32), k, WX)
         extras["fp32_axpy"] = {"gvecs": N / (ms_f32 * 1e-3) / 1e9, "ms": ms_f32,
                                "GBs": 36.0 * N / (ms_f32 * 1e-3) / 1e9}
         extras["speedup_vs_fp32"] = ms_f32 / ms
@@ -397,7 +417,7 @@ def main():
             hb[:, :3] = b32
             hc = torch.empty_like(ha)
             iv = (ha.view(torch.int16), hb.view(torch.int16), hc.view(torch.int16))
-            ms_h = timed(torch, lambda: vc.vcb_axpy_h4(kind, ALPHA, *iv), k, 2)
+            ms_h = timed(torch, lambda: vc.vcb_axpy_h4(kind, ALPHA, *iv), k, WX)
             rec = {"gvecs": N / (ms_h * 1e-3) / 1e9, "ms": ms_h, "GBs": 24.0 * N / (ms_h * 1e-3) / 1e9}
             if kind == "f16":
                 big = (a32.abs() > 65504).any(dim=1).sum().item()
@@ -410,19 +430,19 @@ def main():
         # attainable bandwidth: copy of 2 x 12 N bytes
         src = a32.view(-1)
         dst = torch.empty_like(src)
-        ms_cp = timed(torch, lambda: vc.vcb_copy(src, dst), k, 2)
+        ms_cp = timed(torch, lambda: vc.vcb_copy(src, dst), k, WX)
         copy_gbs = 2.0 * 12 * N / (ms_cp * 1e-3) / 1e9
         extras["copy"] = {"GBs": copy_gbs, "ms": ms_cp, "bytes": 24 * N}
         extras["axpy_frac_of_copy_bw"] = achieved / copy_gbs
         del dst
         # encode / decode / reductions of the same data
-        ms_enc = timed(torch, lambda: vc.vc_encode(c, a32, wc), k, 2)
+        ms_enc = timed(torch, lambda: vc.vc_encode(c, a32, wc), k, WX)
         xyz = torch.empty_like(a32)
-        ms_dec = timed(torch, lambda: vc.vc_decode(c, wa, xyz), k, 2)
+        ms_dec = timed(torch, lambda: vc.vc_decode(c, wa, xyz), k, WX)
         del xyz
         out1 = torch.empty(1, dtype=torch.float32, device=dev)
-        ms_dot = timed(torch, lambda: vc.vc_dot(c, wa, wb, out1), k, 2)
-        ms_n2 = timed(torch, lambda: vc.vc_norm2(c, wa, out1), k, 2)
+        ms_dot = timed(torch, lambda: vc.vc_dot(c, wa, wb, out1), k, WX)
+        ms_n2 = timed(torch, lambda: vc.vc_norm2(c, wa, out1), k, WX)
         extras["encode"] = {"gvecs": N / (ms_enc * 1e-3) / 1e9, "GBs": 20.0 * N / (ms_enc * 1e-3) / 1e9}
         extras["decode"] = {"gvecs": N / (ms_dec * 1e-3) / 1e9, "GBs": 20.0 * N / (ms_dec * 1e-3) / 1e9}
         extras["dot"] = {"gvecs": N / (ms_dot * 1e-3) / 1e9, "GBs": 16.0 * N / (ms_dot * 1e-3) / 1e9}
@@ -431,7 +451,7 @@ def main():
         # the other encoder precision on the same operands
         other = "f32" if args.precision == "f64" else "f64"
         co_ = vc.codec(precision=other)
-        ms_o = timed(torch, lambda: vc.vc_axpy(co_, ALPHA, wa, wb, wc), k, 2)
+        ms_o = timed(torch, lambda: vc.vc_axpy(co_, ALPHA, wa, wb, wc), k, WX)
         extras[f"axpy_encoder_{other}"] = {"gvecs": N / (ms_o * 1e-3) / 1e9, "ms": ms_o,
                                            "GBs": 24.0 * N / (ms_o * 1e-3) / 1e9,
                                            "speedup_vs_fp32": extras["fp32_axpy"]["ms"] / ms_o}
@@ -446,7 +466,7 @@ def main():
             cv = vc.codec(precision=args.precision, **kw)
             va_ = vc.vc_encode(cv, a32)
             vb_ = vc.vc_encode(cv, b32)
-            msv = timed(torch, lambda: vc.vc_axpy(cv, ALPHA, va_, vb_, wc), k, 2)
+            msv = timed(torch, lambda: vc.vc_axpy(cv, ALPHA, va_, vb_, wc), k, WX)
             var[name] = {"gvecs": N / (msv * 1e-3) / 1e9, "GBs": 24.0 * N / (msv * 1e-3) / 1e9}
             log(f"variant {name}: {msv:.3f} ms")
             del va_, vb_

@@ -95,7 +95,7 @@ static int prec_index(int precision)
 vc_status vcx_set_stream_config(int precision, int block, int vpt, int nt)
 {
   const int p = prec_index(precision);
-  if (p < -1 || (vpt != 2 && vpt != 4)) return VC_ERROR_UNSUPPORTED_CODEC;
+  if (p < -1 || (vpt != 2 && vpt != 4 && vpt != 8)) return VC_ERROR_UNSUPPORTED_CODEC;
   return set_axpy_cfg(p, block, vpt / 2, nt);
 }
 

@@ -546,11 +546,11 @@ VC_DI uint64_t encode_vec32(float x, float y, float z, const Params& P)
 
 // Level coordinate of atan2(num, den), num, den >= 0: V = Kq atan2/(pi/2) (den >= 0),
 // 2 Kq - that (den < 0), with C = Kq/(pi/2), plus `add` (a multiple of 1/2).
-VC_DI double angle_levels64(double num, double den, bool den_neg, double Kq_half, double C, double add = 0.0)
+// mx = max(num, den), mn = min(num, den), swap = num > den.
+VC_DI double angle_levels64_mm(double mx, double mn, bool swap, bool den_neg, double Kq_half, double C,
+                               double add = 0.0)
 {
   constexpr double T8 = 0.41421356237309503;      // tan(pi/8)
-  const bool swap = num > den;
-  const double mx = __builtin_fmax(num, den), mn = __builtin_fmin(num, den);
   const bool R = mn > T8 * mx;
   // (nu, de) = R ? (mn - mx, mn + mx) : (mn, mx), as FMAs with a 0/1 factor (each one rounding,
   // or exact when the factor is 0)
@@ -573,6 +573,11 @@ VC_DI double angle_levels64(double num, double den, bool den_neg, double Kq_half
   const double k0 = swap ? 2.0 : (den_neg ? 4.0 : 0.0);
   const double k = fma64_(sgn, Rd, k0);
   return fma64_(C, sgn * at, fma64_(k, Kq_half, add));
+}
+
+VC_DI double angle_levels64(double num, double den, bool den_neg, double Kq_half, double C, double add = 0.0)
+{
+  return angle_levels64_mm(__builtin_fmax(num, den), __builtin_fmin(num, den), num > den, den_neg, Kq_half, C, add);
 }
 
 // Companded level distance from the centre: K h(q/K) for q = K |u| >= 0.
@@ -605,9 +610,11 @@ VC_DI double compand64(double q, double invK, const Params& P)
 template <class L, int MODE>
 VC_DI uint64_t encode_vec64(float x, float y, float z, const Params& P)
 {
-  // |x|, |y|, |z| (the signs are taken from the inputs below); exact, and squares exact in FP64
-  const double X = (double)__builtin_fabsf(x), Y = (double)__builtin_fabsf(y), Z = (double)__builtin_fabsf(z);
-  const double R2 = fma64_(X, X, Y * Y);          // rho^2, one rounding
+  // max and min of |x|, |y| (for theta's octant reduction) and |z|, taken in single precision and
+  // converted exactly; the squares are exact in FP64.  The signs come from the inputs below.
+  const float ax = __builtin_fabsf(x), ay = __builtin_fabsf(y);
+  const double Mx = (double)fmax_(ax, ay), Mn = (double)fmin_(ax, ay), Z = (double)__builtin_fabsf(z);
+  const double R2 = fma64_(Mx, Mx, Mn * Mn);      // rho^2, one rounding
   const double S = fma64_(Z, Z, R2);              // r^2, two roundings (2^-52)
   // a finite float squares to below 2^256, so S is finite exactly when every component is; the
   // squares of nonzero floats are normal doubles, so S is zero only for the zero vector
@@ -658,7 +665,7 @@ VC_DI uint64_t encode_vec64(float x, float y, float z, const Params& P)
 
   // ---- theta: |Q| = Kt |theta|/pi; n = base + floor(+-|Q| (+1/2 if n_theta_max is even))
   const bool yneg = y < 0.0f, xneg = x < 0.0f, zneg = z < 0.0f;
-  double Q = angle_levels64(Y, X, xneg, 0.25 * P.Kt64, P.Ct64);
+  double Q = angle_levels64_mm(Mx, Mn, ay > ax, xneg, 0.25 * P.Kt64, P.Ct64);
   if ((MODE == TANH || MODE == COS) && P.comp_t) Q = compand64<MODE>(Q, P.invKt64, P);
   uint32_t nth;
   if (MODE == FRAC) {

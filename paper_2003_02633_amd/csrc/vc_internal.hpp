@@ -14,7 +14,7 @@ namespace vc {
 // launch configuration of the streaming axpy (chosen by the autotuner, paper_2003_02633_amd/tune.py)
 struct StreamCfg {
   int block;       // threads per block
-  int vpt;         // vectors per thread and grid step (2 or 4)
+  int vpt;         // pairs of codes per lane and grid step (1, 2, or 4 with 256 or 512 threads)
   int nt;          // non-temporal loads/stores
 };
 StreamCfg stream_cfg(int prec);                                   // prec: PREC_F32 / PREC_F64

@@ -219,7 +219,7 @@ StreamCfg stream_cfg(int prec) { return g_axpy_cfg[prec == PREC_F64 ? 1 : 0]; }
 vc_status set_axpy_cfg(int prec, int block, int vpt, int nt)
 {
   const bool okb = block == 128 || block == 256 || block == 512;
-  const bool oku = vpt == 1 || vpt == 2;   // grid steps of 2 codes per lane
+  const bool oku = vpt == 1 || vpt == 2 || (vpt == 4 && block >= 256);   // grid steps of 2 codes per lane
   if (!okb || !oku || (nt != 0 && nt != 1) || prec < -1 || prec > 1) return VC_ERROR_UNSUPPORTED_CODEC;
   for (int p = 0; p < 2; p++)
     if (prec < 0 || prec == p) g_axpy_cfg[p] = {block, vpt, nt};
@@ -250,20 +250,24 @@ static vc_status axpy_t(const Resolved& R, float alpha, const uint64_t* a, const
   // tuned variants for the default layout and uniform quantisation; other codecs use 256 x 1, NT
   if constexpr (std::is_same<L, L0722>::value && MODE == PLAIN) {
     const StreamCfg g = g_axpy_cfg[PREC == PREC_F64 ? 1 : 0];
-    const int key = (g.block == 128 ? 0 : g.block == 256 ? 1 : 2) * 4 + (g.vpt == 2 ? 2 : 0) + g.nt;
+    const int key = (g.block == 128 ? 0 : g.block == 256 ? 1 : 2) * 6 + (g.vpt == 4 ? 4 : g.vpt == 2 ? 2 : 0) + g.nt;
     switch (key) {
       case 0: return axpy_launch<L, MODE, PREC, 128, 1, false>(R, alpha, a, b, c, n, dump, s);
       case 1: return axpy_launch<L, MODE, PREC, 128, 1, true>(R, alpha, a, b, c, n, dump, s);
       case 2: return axpy_launch<L, MODE, PREC, 128, 2, false>(R, alpha, a, b, c, n, dump, s);
       case 3: return axpy_launch<L, MODE, PREC, 128, 2, true>(R, alpha, a, b, c, n, dump, s);
-      case 4: return axpy_launch<L, MODE, PREC, 256, 1, false>(R, alpha, a, b, c, n, dump, s);
-      case 5: return axpy_launch<L, MODE, PREC, 256, 1, true>(R, alpha, a, b, c, n, dump, s);
-      case 6: return axpy_launch<L, MODE, PREC, 256, 2, false>(R, alpha, a, b, c, n, dump, s);
-      case 7: return axpy_launch<L, MODE, PREC, 256, 2, true>(R, alpha, a, b, c, n, dump, s);
-      case 8: return axpy_launch<L, MODE, PREC, 512, 1, false>(R, alpha, a, b, c, n, dump, s);
-      case 9: return axpy_launch<L, MODE, PREC, 512, 1, true>(R, alpha, a, b, c, n, dump, s);
-      case 10: return axpy_launch<L, MODE, PREC, 512, 2, false>(R, alpha, a, b, c, n, dump, s);
-      default: return axpy_launch<L, MODE, PREC, 512, 2, true>(R, alpha, a, b, c, n, dump, s);
+      case 6: return axpy_launch<L, MODE, PREC, 256, 1, false>(R, alpha, a, b, c, n, dump, s);
+      case 7: return axpy_launch<L, MODE, PREC, 256, 1, true>(R, alpha, a, b, c, n, dump, s);
+      case 8: return axpy_launch<L, MODE, PREC, 256, 2, false>(R, alpha, a, b, c, n, dump, s);
+      case 9: return axpy_launch<L, MODE, PREC, 256, 2, true>(R, alpha, a, b, c, n, dump, s);
+      case 10: return axpy_launch<L, MODE, PREC, 256, 4, false>(R, alpha, a, b, c, n, dump, s);
+      case 11: return axpy_launch<L, MODE, PREC, 256, 4, true>(R, alpha, a, b, c, n, dump, s);
+      case 12: return axpy_launch<L, MODE, PREC, 512, 1, false>(R, alpha, a, b, c, n, dump, s);
+      case 13: return axpy_launch<L, MODE, PREC, 512, 1, true>(R, alpha, a, b, c, n, dump, s);
+      case 14: return axpy_launch<L, MODE, PREC, 512, 2, false>(R, alpha, a, b, c, n, dump, s);
+      case 15: return axpy_launch<L, MODE, PREC, 512, 2, true>(R, alpha, a, b, c, n, dump, s);
+      case 16: return axpy_launch<L, MODE, PREC, 512, 4, false>(R, alpha, a, b, c, n, dump, s);
+      default: return axpy_launch<L, MODE, PREC, 512, 4, true>(R, alpha, a, b, c, n, dump, s);
     }
   } else {
     return axpy_launch<L, MODE, PREC, 256, 1, true>(R, alpha, a, b, c, n, dump, s);

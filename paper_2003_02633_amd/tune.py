@@ -19,7 +19,7 @@ import os
 import sys
 
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning", "mi355x_axpy.txt")
-CONFIGS = [(b, v, t) for b in (128, 256, 512) for v in (2, 4) for t in (1, 0)]
+CONFIGS = [(b, v, t) for b in (128, 256, 512) for v in (2, 4, 8) for t in (1, 0) if v < 8 or b >= 256]
 
 
 def sweep(n: int = 1 << 27, precision: str = "f64", steps: int = 10, warmup: int = 2, log=print):

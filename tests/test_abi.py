@@ -169,6 +169,9 @@ def test_tuning_cache_parsing(lib, tmp_path):
         assert lib.vcx_load_tuning(str(f).encode()) == 1
         assert lib.vcx_set_stream_config(-1, 100, 2, 1) == 3
         assert lib.vcx_set_stream_config(-1, 256, 3, 1) == 3
+        assert lib.vcx_set_stream_config(-1, 128, 8, 1) == 3       # 8 per thread needs >= 256 threads
+        assert lib.vcx_set_stream_config(0, 512, 8, 1) == 0       # VC_PREC_F64
+        assert vc.get_stream_config("f64") == (512, 8, 1)
         assert lib.vcx_load_tuning(str(tmp_path / "missing").encode()) == 1
     finally:
         for p, (b, v, t) in saved.items():
