@@ -15,15 +15,19 @@
 //     operand rows k >= cols and elements past the end use the zero code, which decodes to 0;
 //   * M is staged once per workgroup in LDS, transposed (A[k][row], row stride RS = rows rounded
 //     up to 24 mod 32 words, so the four quarters hit different banks); rows beyond `rows` are
-//     read clamped and never stored.
-// A workgroup is 4 waves (64 elements per step), persistent over the element tiles.
+//     read clamped and never stored;
+//   * the results leave through LDS: a lane's accumulators are 4 rows of one element, which
+//     written directly make 64 scattered 12-byte pieces per store; staged per 16-row block, each
+//     element's rows are contiguous and consecutive lanes store consecutive 8-byte pairs.
+// A workgroup is 8 waves (128 elements per step) sharing one copy of M, one workgroup per CU,
+// persistent over the element tiles.
 #include "vc_internal.hpp"
 
 namespace vc {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int APPLY_WAVES = 4;
+constexpr int APPLY_WAVES = 8;
 constexpr int APPLY_EPW = 16;      // elements per wave
 
 // A load the optimiser keeps where it is written (a relaxed wavefront-scope atomic load is an
@@ -39,9 +43,10 @@ inline __host__ __device__ int apply_rs(int rows) { return rows + ((24 - rows % 
 template <class L, int MODE, int MT>
 __global__ __launch_bounds__(64 * APPLY_WAVES) void k_apply(const float* __restrict__ M, int rows, int cols,
                                                               int KS, int RS, const uint64_t* __restrict__ U,
-                                                              float* __restrict__ out, size_t n_elem, Params P)
+                                                              float* __restrict__ out, size_t n_elem, int pairs,
+                                                              Params P)
 {
-  extern __shared__ float As[];  // [4*KS][RS], transposed, zero for k >= cols
+  extern __shared__ float As[];  // [4*KS][RS], transposed, zero for k >= cols; then per-wave staging
   const int KP = 4 * KS;
   for (int i = threadIdx.x; i < KP * RS; i += blockDim.x) {
     const int k = i / RS, r = i - k * RS;
@@ -92,21 +97,43 @@ __global__ __launch_bounds__(64 * APPLY_WAVES) void k_apply(const float* __restr
       for (int m = 0; m < MT; m++) acc[m][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[m], bz, acc[m][2], 0, 0, 0);
     }
     // D[i][jj] at lane jj + 16 (i/4), register i%4: this lane holds rows 16m + 4q + (0..3) of
-    // element e, for the three components
-    if (e_ok) {
-      float* oe = out + e * (size_t)rows * 3;
+    // element e, for the three components.  Each 16-row block is staged through this wave's LDS
+    // area as 16 element blocks of 48 floats and written back with consecutive lanes on
+    // consecutive 8-byte pairs (an element's block of rows is contiguous in `out`).
+    float* st = As + KP * RS + wave * (16 * 48);
+    const size_t t0 = t * APPLY_EPW;
 #pragma unroll
-      for (int m = 0; m < MT; m++) {
+    for (int m = 0; m < MT; m++) {
 #pragma unroll
-        for (int rr = 0; rr < 4; rr++) {
-          const int row = 16 * m + 4 * q + rr;
-          if (row < rows) {
-            oe[3 * row + 0] = acc[m][0][rr];
-            oe[3 * row + 1] = acc[m][1][rr];
-            oe[3 * row + 2] = acc[m][2][rr];
+      for (int rr = 0; rr < 4; rr++)
+#pragma unroll
+        for (int c = 0; c < 3; c++) st[j * 48 + (4 * q + rr) * 3 + c] = acc[m][c][rr];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const int nr = rows - 16 * m < 16 ? rows - 16 * m : 16;   // rows of this block (>= 1)
+      if (nr == 16 && pairs) {
+#pragma unroll
+        for (int i = 0; i < 6; i++) {
+          const int f2 = i * 64 + lane;             // pair index over 16 elements x 24 pairs
+          const int el = f2 / 24, off = 2 * (f2 - el * 24);
+          const size_t eg = t0 + el;
+          if (eg < n_elem) {
+            const float2 v = *(const float2*)(st + el * 48 + off);
+            *(float2*)(out + eg * (size_t)rows * 3 + 48 * m + off) = v;
           }
         }
+      } else {
+        const int nb = 3 * nr;
+        for (int f = lane; f < 16 * nb; f += 64) {
+          const int el = f / nb, off = f - el * nb;
+          const size_t eg = t0 + el;
+          if (eg < n_elem) out[eg * (size_t)rows * 3 + 48 * m + off] = st[el * 48 + off];
+        }
       }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
   }
 }
@@ -117,7 +144,7 @@ static vc_status apply_mt(const Resolved& R, const float* M, int rows, int cols,
 {
   const int KS = (cols + 3) / 4;
   const int RS = apply_rs(rows);
-  const size_t lds = (size_t)4 * KS * RS * sizeof(float);
+  const size_t lds = ((size_t)4 * KS * RS + (size_t)APPLY_WAVES * 16 * 48) * sizeof(float);
   int dev = 0, ncu = 256;
   if (hipGetDevice(&dev) == hipSuccess) {
     hipDeviceProp_t prop;
@@ -125,15 +152,17 @@ static vc_status apply_mt(const Resolved& R, const float* M, int rows, int cols,
   }
   const size_t ntiles = (n_elem + APPLY_EPW - 1) / APPLY_EPW;
   size_t grid = (ntiles + APPLY_WAVES - 1) / APPLY_WAVES;
-  const size_t cap = (size_t)ncu * 2;               // two resident workgroups per CU
+  const size_t cap = (size_t)ncu;                   // one resident workgroup per CU
   if (grid > cap) grid = cap;
   if (grid < 1) grid = 1;
   if (lds > 64 * 1024 &&
       hipFuncSetAttribute((const void*)k_apply<L, MODE, MT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
           hipSuccess)
     return VC_ERROR_HIP;
+  // 8-byte stores need an even row length (3 rows) and an 8-byte aligned output
+  const int pairs = (rows % 2 == 0) && (((uintptr_t)out & 7u) == 0);
   hipLaunchKernelGGL((k_apply<L, MODE, MT>), dim3((unsigned)grid), dim3(64 * APPLY_WAVES), lds, s, M, rows, cols,
-                     KS, RS, U, out, n_elem, R.P);
+                     KS, RS, U, out, n_elem, pairs, R.P);
   return launch_status();
 }
 
