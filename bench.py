@@ -86,9 +86,9 @@ def read_valu(n: int):
 
 
 # Side-by-side timings warm up by time, not count: the clocks drop within milliseconds of idle
-# (host-side set-up between measurements) and take about 20 ms of load to come back up.
+# (host-side set-up between measurements) and take tens of milliseconds of load to come back up.
 WX = None
-SETTLE_MS = 25.0
+SETTLE_MS = 100.0
 
 
 def timed(torch, fn, steps: int, warmup) -> float:
@@ -97,14 +97,13 @@ def timed(torch, fn, steps: int, warmup) -> float:
     import time
 
     if warmup is None:
-        # one call to size the rest, then enough back-to-back calls to fill SETTLE_MS
+        # back-to-back calls, checked every 8, until SETTLE_MS of wall time has passed
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        fn()
-        torch.cuda.synchronize()
-        t1 = max((time.perf_counter() - t0) * 1e3, 1e-3)
-        for _ in range(min(10000, int(SETTLE_MS / t1) + 1)):
-            fn()
+        while (time.perf_counter() - t0) * 1e3 < SETTLE_MS:
+            for _ in range(8):
+                fn()
+            torch.cuda.synchronize()
     else:
         for _ in range(warmup):
             fn()
@@ -329,8 +328,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=25,
-                    help="untimed launches first; the clocks take about 20 ms of load to settle")
+    ap.add_argument("--warmup", type=int, default=50,
+                    help="untimed launches first; the clocks take tens of milliseconds of load to settle")
     ap.add_argument("--n", type=int, default=1 << 27)
     ap.add_argument("--quick", action="store_true", help="skip the side-by-side extras")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")

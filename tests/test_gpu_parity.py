@@ -207,6 +207,31 @@ def test_axpy_ragged_and_unaligned(torch_dev, n, prec):
     assert np.array_equal(down(ta, True)[:n], ref_gpu)
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_axpy_every_launch_config(torch_dev, prec):
+    """Every launch configuration the autotuner may pick gives the codes of the default one, on
+    several whole tiles plus a ragged tail (and those codes follow the encode rule)."""
+    from paper_2003_02633_amd import tune
+    say(f"case: axpy launch configurations {prec}")
+    torch = torch_dev
+    c, co = vc.codec(precision=prec), O.codec()
+    n = 3 * 2 * 512 * 4 + 77
+    xa, xb = inputs.sphere_loguniform(n, 21), inputs.sphere_loguniform(n, 22)
+    wa, wb = O.encode(co, xa), O.encode(co, xb)
+    ref = _check_axpy(torch, c, co, wa, wb, ALPHA, f"axpy default config {prec}")
+    ta, tb = up(torch, wa), up(torch, wb)
+    saved = vc.get_stream_config(prec)
+    try:
+        for blk, vpt, nt in tune.CONFIGS:
+            vc.set_stream_config(blk, vpt, nt, prec)
+            out = torch.zeros(n, dtype=torch.int64, device="cuda")
+            vc.vc_axpy(c, ALPHA, ta, tb, out)
+            torch.cuda.synchronize()
+            assert np.array_equal(down(out, True), ref), (blk, vpt, nt)
+    finally:
+        vc.set_stream_config(*saved, prec)
+
+
 def test_encode_decode_ragged_unaligned(torch_dev):
     torch = torch_dev
     c, co = vc.codec(), O.codec()
