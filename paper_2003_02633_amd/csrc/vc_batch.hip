@@ -131,12 +131,7 @@ __global__ __launch_bounds__(BB) void k_batch(const BatchSeg* __restrict__ segs,
       }
       for (int h = 0; h < cnt; h++) {
         if (dot) {
-          float ax, ay, az, bx, by, bz;
-          decode_vec<L, MODE>(wa[h], P, ax, ay, az);
-          decode_vec<L, MODE>(wb[h], P, bx, by, bz);
-          acc = __builtin_fmaf(ax, bx, acc);
-          acc = __builtin_fmaf(ay, by, acc);
-          acc = __builtin_fmaf(az, bz, acc);
+          acc += dot_pair<L, MODE>(wa[h], wb[h], P);
         } else {
           const float r = decode_mag<L>(wa[h]);
           acc = __builtin_fmaf(r, r, acc);

@@ -175,13 +175,12 @@ VC_DI float decode_mag(uint64_t w)
   return r;
 }
 
-// Cartesian vector of a code: Eq. (a_inv) then Eq. (cart2sphere).
+// The fields of a code: magnitude r_hat (NaN for codes past the fractional split's limit) and
+// the level counts n_theta, n_phi (Eq. q_split for the fractional split).
 template <class L, int MODE>
-VC_DI void decode_vec(uint64_t w, const Params& P, float& ox, float& oy, float& oz)
+VC_DI void decode_fields(uint64_t w, const Params& P, float& r, uint32_t& nth, uint32_t& nph)
 {
-  float r = decode_mag<L>(w);
-
-  uint32_t nth, nph;
+  r = decode_mag<L>(w);
   if (MODE == FRAC) {
     const uint64_t np = w & ((1ull << (L::p + L::t)) - 1ull);
     if (np >= P.limit) r = ubits(0x7fc00000u);
@@ -196,8 +195,16 @@ VC_DI void decode_vec(uint64_t w, const Params& P, float& ox, float& oy, float& 
     nth = (uint32_t)w & ((1u << L::t) - 1u);
     nph = (uint32_t)(w >> L::sh_p) & ((1u << L::p) - 1u);
   }
-  // revolutions: theta_hat/(2 pi) = n/n_max - 1/2, phi_hat/(2 pi) = n/(2 n_max)
-  float rev_t, rev_p;
+}
+
+// x P.r?_h + x P.r?_l: a level count times a reciprocal held as a double-float
+VC_DI float times_dd(float x, float h, float l) { return fma_(x, h, x * l); }
+
+// Angles of the levels in revolutions (Eq. a_inv, §2.5 for the companded maps):
+// theta_hat/(2 pi) = n/n_max - 1/2, phi_hat/(2 pi) = n/(2 n_max) for uniform levels.
+template <int MODE>
+VC_DI void level_revs(uint32_t nth, uint32_t nph, const Params& P, float& rev_t, float& rev_p)
+{
   const float dt = (float)nth - P.half_t;                 // exact
   if (MODE == TANH || MODE == COS) {
     const float hh_t = (2.0f * (float)nth - (float)P.nmax_t) / (float)P.nmax_t;
@@ -214,19 +221,51 @@ VC_DI void decode_vec(uint64_t w, const Params& P, float& ox, float& oy, float& 
     }
     rev_t = 0.5f * ut;
     rev_p = 0.25f * (up + 1.0f);
-    if (!P.comp_t) rev_t = fma_(dt, P.rt_h, dt * P.rt_l);
-    if (!P.comp_p) { const float fp = (float)nph; rev_p = fma_(fp, P.rp_h, fp * P.rp_l); }
+    if (!P.comp_t) rev_t = times_dd(dt, P.rt_h, P.rt_l);
+    if (!P.comp_p) rev_p = times_dd((float)nph, P.rp_h, P.rp_l);
   } else {
-    rev_t = fma_(dt, P.rt_h, dt * P.rt_l);
-    const float fp = (float)nph;
-    rev_p = fma_(fp, P.rp_h, fp * P.rp_l);
+    rev_t = times_dd(dt, P.rt_h, P.rt_l);
+    rev_p = times_dd((float)nph, P.rp_h, P.rp_l);
   }
+}
+
+// Cartesian vector of a code: Eq. (a_inv) then Eq. (cart2sphere).
+template <class L, int MODE>
+VC_DI void decode_vec(uint64_t w, const Params& P, float& ox, float& oy, float& oz)
+{
+  float r;
+  uint32_t nth, nph;
+  decode_fields<L, MODE>(w, P, r, nth, nph);
+  float rev_t, rev_p;
+  level_revs<MODE>(nth, nph, P, rev_t, rev_p);
   const float st = sin_rev(rev_t), ct = cos_rev(rev_t);
   const float sp = sin_rev(rev_p), cp = cos_rev(rev_p);
   const float rs = r * sp;
   ox = rs * ct;
   oy = rs * st;
   oz = r * cp;
+}
+
+// decode(a) . decode(b) in spherical form (Eq. cart2sphere):
+//   r_a r_b (sin phi_a sin phi_b cos(theta_a - theta_b) + cos phi_a cos phi_b),
+// five hardware sine/cosine evaluations instead of the eight of two decodes.  For uniform theta
+// levels the difference of the angles is formed from the exact difference of the level counts.
+template <class L, int MODE>
+VC_DI float dot_pair(uint64_t wa, uint64_t wb, const Params& P)
+{
+  float ra, rb;
+  uint32_t ta, pa, tb, pb;
+  decode_fields<L, MODE>(wa, P, ra, ta, pa);
+  decode_fields<L, MODE>(wb, P, rb, tb, pb);
+  float rta, rpa, rtb, rpb, drev;
+  level_revs<MODE>(ta, pa, P, rta, rpa);
+  level_revs<MODE>(tb, pb, P, rtb, rpb);
+  if (MODE == PLAIN || MODE == FRAC || ((MODE == TANH || MODE == COS) && !P.comp_t))
+    drev = times_dd((float)((int)ta - (int)tb), P.rt_h, P.rt_l);   // |ta - tb| < 2^24: exact
+  else
+    drev = rta - rtb;
+  const float sa = sin_rev(rpa), ca = cos_rev(rpa), sb = sin_rev(rpb), cb = cos_rev(rpb);
+  return (ra * rb) * fma_(sa * sb, cos_rev(drev), ca * cb);
 }
 
 // ------------------------------------------------------------------ encode helpers

@@ -168,12 +168,7 @@ __global__ __launch_bounds__(BS) void k_dot(const uint64_t* __restrict__ a, cons
 {
   float acc = 0.0f;
   for (size_t i = (size_t)blockIdx.x * BS + threadIdx.x; i < n; i += (size_t)gridDim.x * BS) {
-    float ax, ay, az, bx, by, bz;
-    decode_vec<L, MODE>(a[i], P, ax, ay, az);
-    decode_vec<L, MODE>(b[i], P, bx, by, bz);
-    acc = __builtin_fmaf(ax, bx, acc);
-    acc = __builtin_fmaf(ay, by, acc);
-    acc = __builtin_fmaf(az, bz, acc);
+    acc += dot_pair<L, MODE>(a[i], b[i], P);
   }
   const float s = block_sum<BS>(acc);
   if (threadIdx.x == 0) parts[blockIdx.x] = s;

@@ -32,6 +32,7 @@ def lib():
         vp = C.c_void_p
         L.emu_encode.argtypes = [vp, vp, vp, C.c_size_t]
         L.emu_decode.argtypes = [vp, vp, vp, C.c_size_t]
+        L.emu_dot_pair.argtypes = [vp, vp, vp, vp, C.c_size_t]
         L.emu_exact_norm.argtypes = [C.c_float, C.c_float, C.c_float, C.c_int, C.c_int,
                                      C.POINTER(C.c_uint32), C.POINTER(C.c_int)]
         _lib = L
@@ -53,6 +54,17 @@ def decode(codec, w):
     st = lib().emu_decode(C.addressof(codec), w.ctypes.data, out.ctypes.data, w.shape[0])
     if st:
         raise RuntimeError(f"emu_decode status {st}")
+    return out
+
+
+def dot_pair(codec, wa, wb):
+    """per-pair decode(a) . decode(b) as the kernels form it (spherical form)"""
+    wa = np.ascontiguousarray(np.asarray(wa).astype(np.uint64).reshape(-1))
+    wb = np.ascontiguousarray(np.asarray(wb).astype(np.uint64).reshape(-1))
+    out = np.empty(wa.shape[0], dtype=np.float32)
+    st = lib().emu_dot_pair(C.addressof(codec), wa.ctypes.data, wb.ctypes.data, out.ctypes.data, wa.shape[0])
+    if st:
+        raise RuntimeError(f"emu_dot_pair status {st}")
     return out
 
 

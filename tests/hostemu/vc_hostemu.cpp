@@ -24,6 +24,12 @@ static void dec(const Params& P, const uint64_t* w, float* out, size_t n)
   for (size_t i = 0; i < n; i++) decode_vec<L, MODE>(w[i], P, out[3 * i], out[3 * i + 1], out[3 * i + 2]);
 }
 
+template <class L, int MODE>
+static void dotp(const Params& P, const uint64_t* a, const uint64_t* b, float* out, size_t n)
+{
+  for (size_t i = 0; i < n; i++) out[i] = dot_pair<L, MODE>(a[i], b[i], P);
+}
+
 #define EMU_DISPATCH(R, FN, ...)                      \
   switch ((R).layout * 4 + (R).mode) {                \
     case 0: FN<L0722, PLAIN>(__VA_ARGS__); break;     \
@@ -53,6 +59,15 @@ int emu_decode(const vc_codec* c, const uint64_t* w, float* out, size_t n)
   vc_status st = resolve(c, &R);
   if (st != VC_SUCCESS) return st;
   EMU_DISPATCH(R, dec, R.P, w, out, n);
+  return 0;
+}
+
+int emu_dot_pair(const vc_codec* c, const uint64_t* a, const uint64_t* b, float* out, size_t n)
+{
+  Resolved R;
+  vc_status st = resolve(c, &R);
+  if (st != VC_SUCCESS) return st;
+  EMU_DISPATCH(R, dotp, R.P, a, b, out, n);
   return 0;
 }
 

@@ -92,6 +92,23 @@ def test_emulated_decode_matches_oracle(layout, mode, kw):
     assert nan_ok and err <= 1e-6
 
 
+@pytest.mark.parametrize("layout,mode,kw", [v for v in VARIANTS if not hasattr(v, "marks") or not v.marks])
+def test_emulated_dot_pair_matches_oracle(layout, mode, kw):
+    """The kernels' dot product of two codes, taken in spherical form (the angle difference from
+    the level counts), against the FP64 dot product of the oracle's decodes, per pair."""
+    c, co = _pair(layout, mode, kw)
+    xa, xb = inputs.sphere_loguniform(20000, 31), inputs.sphere_loguniform(20000, 32)
+    wa, wb = O.encode(co, xa), O.encode(co, xb)
+    wb[:50] = wa[:50]                                  # equal angles (theta difference zero)
+    wa[50:60] = 0                                      # the zero code
+    got = H.dot_pair(c, wa, wb).astype(np.float64)
+    A, B = O.decode64(co, wa), O.decode64(co, wb)
+    ref = np.einsum("ij,ij->i", A, B)
+    scale = np.linalg.norm(A, axis=1) * np.linalg.norm(B, axis=1)
+    assert np.all(got[50:60] == 0.0)
+    assert np.all(np.abs(got - ref) <= 1e-6 * scale), np.max(np.abs(got - ref) / np.maximum(scale, 1e-300))
+
+
 def test_emulated_exact_norm_path():
     """The exact integer magnitude path (taken near rounding midpoints) is exact."""
     g = np.random.default_rng(10)
