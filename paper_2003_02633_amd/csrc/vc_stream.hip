@@ -83,30 +83,6 @@ __global__ __launch_bounds__(BS) void k_axpy(const uint64_t* __restrict__ a, con
 }
 
 // ------------------------------------------------------------------ encode / decode
-// Groups of 4 vectors per lane: 48 bytes of float32 AoS (3 x 16-byte accesses)
-// and 32 bytes of codes (2 x 16-byte accesses).  Requires 16-byte aligned
-// pointers (checked by the launcher, which otherwise uses the scalar kernel).
-template <class L, int MODE, int PREC, int BS, bool NT>
-__global__ __launch_bounds__(BS) void k_encode4(const float* __restrict__ xyz, uint64_t* __restrict__ codes,
-                                                size_t n, Params P)
-{
-  const size_t ng = n / 4;
-  for (size_t g = (size_t)blockIdx.x * BS + threadIdx.x; g < ng; g += (size_t)gridDim.x * BS) {
-    const f32x4* src = (const f32x4*)(xyz + 12 * g);
-    const f32x4 q0 = ld<NT>(src), q1 = ld<NT>(src + 1), q2 = ld<NT>(src + 2);
-    u64x2 o0, o1;
-    o0[0] = encode_vec<L, MODE, PREC>(q0[0], q0[1], q0[2], P);
-    o0[1] = encode_vec<L, MODE, PREC>(q0[3], q1[0], q1[1], P);
-    o1[0] = encode_vec<L, MODE, PREC>(q1[2], q1[3], q2[0], P);
-    o1[1] = encode_vec<L, MODE, PREC>(q2[1], q2[2], q2[3], P);
-    u64x2* dst = (u64x2*)(codes + 4 * g);
-    st<NT>(dst, o0);
-    st<NT>(dst + 1, o1);
-  }
-  for (size_t i = 4 * ng + (size_t)blockIdx.x * BS + threadIdx.x; i < n; i += (size_t)gridDim.x * BS)
-    codes[i] = encode_vec<L, MODE, PREC>(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], P);
-}
-
 template <class L, int MODE, int PREC, int BS>
 __global__ __launch_bounds__(BS) void k_encode1(const float* __restrict__ xyz, uint64_t* __restrict__ codes,
                                                 size_t n, Params P)
@@ -115,26 +91,79 @@ __global__ __launch_bounds__(BS) void k_encode1(const float* __restrict__ xyz, u
     codes[i] = encode_vec<L, MODE, PREC>(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], P);
 }
 
+// Encode and decode in wave tiles of 256 vectors, so that every load and store instruction of a
+// wave covers 1 KiB contiguous: lane l holds codes 2l, 2l+1 and 128 + 2l, 129 + 2l (two 16-byte
+// accesses), and the float32 AoS side (3 KiB per tile) passes through LDS (3 KiB per wave) as
+// three 16-byte accesses per lane.  Requires 16-byte aligned pointers (checked by the launcher,
+// which otherwise uses the one-vector-per-lane kernels); the tail past the last whole tile is
+// done one vector per lane.
 template <class L, int MODE, int BS, bool NT>
-__global__ __launch_bounds__(BS) void k_decode4(const uint64_t* __restrict__ codes, float* __restrict__ xyz,
-                                                size_t n, Params P)
+__global__ __launch_bounds__(BS) void k_decode_w(const uint64_t* __restrict__ codes, float* __restrict__ xyz,
+                                                 size_t n, Params P)
 {
-  const size_t ng = n / 4;
-  for (size_t g = (size_t)blockIdx.x * BS + threadIdx.x; g < ng; g += (size_t)gridDim.x * BS) {
-    const u64x2* src = (const u64x2*)(codes + 4 * g);
-    const u64x2 w0 = ld<NT>(src), w1 = ld<NT>(src + 1);
+  __shared__ float stage[BS / 64][256 * 3];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  float* sw = stage[wv];
+  const size_t ntile = n / 256;
+  for (size_t t = (size_t)blockIdx.x * (BS / 64) + wv; t < ntile; t += (size_t)gridDim.x * (BS / 64)) {
+    const u64x2* src = (const u64x2*)(codes + 256 * t);
+    const u64x2 w0 = ld<NT>(src + lane), w1 = ld<NT>(src + 64 + lane);
     float v[12];
     decode_vec<L, MODE>(w0[0], P, v[0], v[1], v[2]);
     decode_vec<L, MODE>(w0[1], P, v[3], v[4], v[5]);
     decode_vec<L, MODE>(w1[0], P, v[6], v[7], v[8]);
     decode_vec<L, MODE>(w1[1], P, v[9], v[10], v[11]);
-    f32x4* dst = (f32x4*)(xyz + 12 * g);
-    st<NT>(dst, f32x4{v[0], v[1], v[2], v[3]});
-    st<NT>(dst + 1, f32x4{v[4], v[5], v[6], v[7]});
-    st<NT>(dst + 2, f32x4{v[8], v[9], v[10], v[11]});
+#pragma unroll
+    for (int i = 0; i < 6; i++) { sw[6 * lane + i] = v[i]; sw[384 + 6 * lane + i] = v[6 + i]; }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    f32x4* dst = (f32x4*)(xyz + 768 * t);
+#pragma unroll
+    for (int k = 0; k < 3; k++) st<NT>(dst + 64 * k + lane, *(const f32x4*)(sw + 4 * (64 * k + lane)));
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
-  for (size_t i = 4 * ng + (size_t)blockIdx.x * BS + threadIdx.x; i < n; i += (size_t)gridDim.x * BS)
+  for (size_t i = 256 * ntile + (size_t)blockIdx.x * BS + threadIdx.x; i < n; i += (size_t)gridDim.x * BS)
     decode_vec<L, MODE>(codes[i], P, xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2]);
+}
+
+template <class L, int MODE, int PREC, int BS, bool NT>
+__global__ __launch_bounds__(BS) void k_encode_w(const float* __restrict__ xyz, uint64_t* __restrict__ codes,
+                                                 size_t n, Params P)
+{
+  __shared__ float stage[BS / 64][256 * 3];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  float* sw = stage[wv];
+  const size_t ntile = n / 256;
+  for (size_t t = (size_t)blockIdx.x * (BS / 64) + wv; t < ntile; t += (size_t)gridDim.x * (BS / 64)) {
+    const f32x4* src = (const f32x4*)(xyz + 768 * t);
+    f32x4 q[3];
+#pragma unroll
+    for (int k = 0; k < 3; k++) q[k] = ld<NT>(src + 64 * k + lane);
+#pragma unroll
+    for (int k = 0; k < 3; k++) *(f32x4*)(sw + 4 * (64 * k + lane)) = q[k];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    float v[12];
+#pragma unroll
+    for (int i = 0; i < 6; i++) { v[i] = sw[6 * lane + i]; v[6 + i] = sw[384 + 6 * lane + i]; }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    u64x2 o0, o1;
+    o0[0] = encode_vec<L, MODE, PREC>(v[0], v[1], v[2], P);
+    o0[1] = encode_vec<L, MODE, PREC>(v[3], v[4], v[5], P);
+    o1[0] = encode_vec<L, MODE, PREC>(v[6], v[7], v[8], P);
+    o1[1] = encode_vec<L, MODE, PREC>(v[9], v[10], v[11], P);
+    u64x2* dst = (u64x2*)(codes + 256 * t);
+    st<NT>(dst + lane, o0);
+    st<NT>(dst + 64 + lane, o1);
+  }
+  for (size_t i = 256 * ntile + (size_t)blockIdx.x * BS + threadIdx.x; i < n; i += (size_t)gridDim.x * BS)
+    codes[i] = encode_vec<L, MODE, PREC>(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], P);
 }
 
 template <class L, int MODE, int BS>
@@ -276,7 +305,7 @@ static vc_status encode_t(const Resolved& R, const float* xyz, uint64_t* codes, 
   const bool aligned = (((uintptr_t)xyz | (uintptr_t)codes) & 15u) == 0;
   if (aligned) {
     const unsigned grid = grid_for(n, (size_t)4 * BS, 1u << 30);
-    hipLaunchKernelGGL((k_encode4<L, MODE, PREC, BS, true>), dim3(grid), dim3(BS), 0, s, xyz, codes, n, R.P);
+    hipLaunchKernelGGL((k_encode_w<L, MODE, PREC, BS, true>), dim3(grid), dim3(BS), 0, s, xyz, codes, n, R.P);
   } else {
     const unsigned grid = grid_for(n, (size_t)BS, 1u << 30);
     hipLaunchKernelGGL((k_encode1<L, MODE, PREC, BS>), dim3(grid), dim3(BS), 0, s, xyz, codes, n, R.P);
@@ -291,7 +320,7 @@ static vc_status decode_t(const Resolved& R, const uint64_t* codes, float* xyz, 
   const bool aligned = (((uintptr_t)xyz | (uintptr_t)codes) & 15u) == 0;
   if (aligned) {
     const unsigned grid = grid_for(n, (size_t)4 * BS, 1u << 30);
-    hipLaunchKernelGGL((k_decode4<L, MODE, BS, true>), dim3(grid), dim3(BS), 0, s, codes, xyz, n, R.P);
+    hipLaunchKernelGGL((k_decode_w<L, MODE, BS, true>), dim3(grid), dim3(BS), 0, s, codes, xyz, n, R.P);
   } else {
     const unsigned grid = grid_for(n, (size_t)BS, 1u << 30);
     hipLaunchKernelGGL((k_decode1<L, MODE, BS>), dim3(grid), dim3(BS), 0, s, codes, xyz, n, R.P);
