@@ -10,21 +10,19 @@
 //   fractional split                         §2.4, Eq. (q_split)
 //   tanh / cosine companding                 §2.5
 //
-// Design (gfx950, FP32 + integer only):
-//   * magnitude: the exact norm is rounded to nearest-even at 1+m bits.  A
-//     double-float (pairs of FP32) evaluation of x^2+y^2+z^2 and of its square
-//     root decides the rounding unless the norm lies within 2^-14 grid units of
-//     a rounding midpoint (about 3 in 10^5 vectors); those lanes take an exact
-//     128-bit integer path.
-//   * angles: both angles are atan2 problems.  Octant reduction to
-//     |b| <= tan(pi/8) (one double-float division), a short polynomial for
-//     atan(b)/b - 1, and the level coordinate carried as a double-float in
-//     level units, so the floor() of Eq. (a_disc) is taken exactly up to
-//     ~2^-24 level units -- far inside one single-precision ulp of the angle.
-//     The half-up ties of the axis directions (theta = 0, phi = pi/2) come out
-//     exactly.
-//   * decode: hardware sin/cos in revolutions (v_sin_f32 / v_cos_f32) of an
-//     exactly formed level offset; accuracy ~1e-7 of |x|.
+// Two encoders with the same contract (every level exact except within one single-precision ulp
+// of the angle from a level boundary; the magnitude rounded to nearest-even from the exact norm):
+//   * FP64-assisted (the default, encode_vec64): squares, norm and ratios in FP64 (on gfx950
+//     an FP64 FMA issues like an FP32 one), an rsqrt / reciprocal seed with one correction
+//     step, an octant reduction to |b| <= tan(pi/8) and a degree-4 polynomial for
+//     atan(b)/b - 1 (relative error 2.5e-9), the level coordinate and its floor in FP64.
+//     Norms within 2^-44 of a rounding midpoint take an exact 128-bit integer path.
+//   * single precision (encode_vec32, FP32 + integer only): the same steps with double-float
+//     (pairs of FP32) arithmetic; the level coordinate is exact to ~2^-24 level units, and
+//     norms within 2^-14 grid units of a midpoint (about 3 in 10^5) take the exact path.
+// In both, the half-up ties of the axis directions (theta = 0, phi = pi/2) come out exactly.
+// Decode: hardware sin/cos in revolutions (v_sin_f32 / v_cos_f32) of an exactly formed level
+// offset, accuracy ~3e-7 of |x|; the dot product of two codes is taken in spherical form.
 //
 // The header also compiles for the host (VC_HOST_EMULATION) with libm stand-ins
 // for the AMDGPU builtins, so the integer and control logic can be exercised
