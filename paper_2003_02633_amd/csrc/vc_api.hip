@@ -12,6 +12,10 @@ namespace vc {
 
 static inline bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
+// the result of an empty reduction, written by a kernel (not a memset node, so that a caller may
+// capture the call in a graph)
+__global__ void k_zero_result(float* out) { out[0] = 0.0f; }
+
 static bool overlaps(const void* p, size_t pb, const void* q, size_t qb)
 {
   uintptr_t a0 = (uintptr_t)p, a1 = a0 + pb, b0 = (uintptr_t)q, b1 = b0 + qb;
@@ -164,7 +168,8 @@ static vc_status reduce_common(const vc_codec* c, const uint64_t* a, const uint6
   if (!d_out) return VC_ERROR_INVALID_VALUE;
   if (!aligned(d_out, 4)) return VC_ERROR_MISALIGNED;
   if (n == 0) {
-    return hipMemsetAsync(d_out, 0, sizeof(float), stream) == hipSuccess ? VC_SUCCESS : VC_ERROR_HIP;
+    hipLaunchKernelGGL(k_zero_result, dim3(1), dim3(1), 0, stream, d_out);
+    return launch_status();
   }
   if (!a || (is_dot && !b)) return VC_ERROR_INVALID_VALUE;
   if (!aligned(a, 8) || (is_dot && !aligned(b, 8))) return VC_ERROR_MISALIGNED;
