@@ -83,6 +83,16 @@ vc_status vcb_gather_f32(const float* src, size_t n_src, const uint32_t* idx, si
 /* dst[0:bytes) = src[0:bytes): the attainable-bandwidth reference.  16-byte aligned. */
 vc_status vcb_copy(const void* src, void* dst, size_t bytes, hipStream_t stream);
 
+/* The codec's resolved constants for the device functions of vc_inline.hpp (the inline use of
+ * the method: encode and decode inside the caller's own kernels, §1 and Alg. fr_fdiv_comp).
+ * Writes `size` bytes of the constants block to params (host memory, owned by the caller), which
+ * a kernel takes by value as vc_inline::Params; size must equal vcx_inline_params_size().
+ * Returns VC_ERROR_INVALID_VALUE for a NULL pointer or a wrong size, and the codec's own
+ * validation errors (VC_ERROR_UNSUPPORTED_CODEC) otherwise.  The kernel must instantiate the
+ * device functions for the codec's layout, mode and encoder precision. */
+vc_status vcx_inline_params(const vc_codec* c, void* params, size_t size);
+size_t vcx_inline_params_size(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -66,6 +66,8 @@ _SIGS = {
     "vcb_axpy_bf16x4": ([C.c_float, _vp, _vp, _vp, C.c_size_t, _vp], C.c_int),
     "vcb_axpy_f16x4": ([C.c_float, _vp, _vp, _vp, C.c_size_t, _vp], C.c_int),
     "vcb_copy": ([_vp, _vp, C.c_size_t, _vp], C.c_int),
+    "vcx_inline_params": ([C.POINTER(vc_codec), _vp, C.c_size_t], C.c_int),
+    "vcx_inline_params_size": ([], C.c_size_t),
     "vcx_set_stream_config": ([C.c_int, C.c_int, C.c_int, C.c_int], C.c_int),
     "vcx_get_stream_config": ([C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
     "vcx_load_tuning": ([C.c_char_p], C.c_int),

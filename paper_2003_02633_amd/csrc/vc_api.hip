@@ -181,6 +181,18 @@ static vc_status reduce_common(const vc_codec* c, const uint64_t* a, const uint6
   return st;
 }
 
+vc_status vcx_inline_params(const vc_codec* c, void* params, size_t size)
+{
+  if (!params || size != sizeof(Params)) return VC_ERROR_INVALID_VALUE;
+  Resolved R;
+  const vc_status st = resolve(c, &R);
+  if (st != VC_SUCCESS) return st;
+  memcpy(params, &R.P, sizeof(Params));
+  return VC_SUCCESS;
+}
+
+size_t vcx_inline_params_size(void) { return sizeof(Params); }
+
 vc_status vc_dot(const vc_codec* c, const uint64_t* a, const uint64_t* b, size_t n, float* d_out,
                  hipStream_t stream)
 {

@@ -4,6 +4,7 @@ import ctypes as C
 import os
 import re
 
+import numpy as np
 import pytest
 
 import paper_2003_02633_amd as vc
@@ -177,6 +178,20 @@ def test_tuning_cache_parsing(lib, tmp_path):
         for p, (b, v, t) in saved.items():
             vc.set_stream_config(b, v, t, p)
     assert vc.get_stream_config("f64") == saved["f64"]
+
+
+def test_inline_params(lib):
+    """the constants block of the inline device API: size checked, codec validated"""
+    size = lib.vcx_inline_params_size()
+    assert 64 <= size <= 4096
+    buf = C.create_string_buffer(size)
+    assert lib.vcx_inline_params(C.byref(vc.codec()), buf, size) == 0
+    assert lib.vcx_inline_params(C.byref(vc.codec()), buf, size - 8) == 1
+    assert lib.vcx_inline_params(C.byref(vc.codec()), None, size) == 1
+    assert lib.vcx_inline_params(C.byref(vc.codec(mode="tanh", precision="f32")), buf, size) == 3
+    # the first fields are n_theta_max and n_phi_max of the default layout
+    nt, npm = np.frombuffer(buf.raw[:8], dtype=np.uint32)
+    assert (nt, npm) == ((1 << 18) - 1, (1 << 17) - 1)
 
 
 def test_error_hist_validation_without_device_work(lib):
