@@ -195,8 +195,17 @@ VC_DI void decode_fields(uint64_t w, const Params& P, float& r, uint32_t& nth, u
   }
 }
 
-// x P.r?_h + x P.r?_l: a level count times a reciprocal held as a double-float
-VC_DI float times_dd(float x, float h, float l) { return fma_(x, h, x * l); }
+// A level count times 1/n_max (or 1/(2 n_max)).  For the uniform levels of every layout
+// n_max = 2^k - 1 (k = 16..18), so 1/n_max = 2^-k (1 + 2^-k + 2^-2k + ...) and its float32
+// rounding 2^-k (1 + 2^-k) is off by 2^-2k <= 2^-32 relative: one product is rounded as well as
+// the exact one.  The fractional split's n_max = T - 1 is arbitrary and takes the double-float
+// reciprocal (h + l).
+template <int MODE>
+VC_DI float times_rcp(float x, float h, float l)
+{
+  if (MODE == FRAC) return fma_(x, h, x * l);
+  return x * h;
+}
 
 // Angles of the levels in revolutions (Eq. a_inv, §2.5 for the companded maps):
 // theta_hat/(2 pi) = n/n_max - 1/2, phi_hat/(2 pi) = n/(2 n_max) for uniform levels.
@@ -219,11 +228,11 @@ VC_DI void level_revs(uint32_t nth, uint32_t nph, const Params& P, float& rev_t,
     }
     rev_t = 0.5f * ut;
     rev_p = 0.25f * (up + 1.0f);
-    if (!P.comp_t) rev_t = times_dd(dt, P.rt_h, P.rt_l);
-    if (!P.comp_p) rev_p = times_dd((float)nph, P.rp_h, P.rp_l);
+    if (!P.comp_t) rev_t = times_rcp<MODE>(dt, P.rt_h, P.rt_l);
+    if (!P.comp_p) rev_p = times_rcp<MODE>((float)nph, P.rp_h, P.rp_l);
   } else {
-    rev_t = times_dd(dt, P.rt_h, P.rt_l);
-    rev_p = times_dd((float)nph, P.rp_h, P.rp_l);
+    rev_t = times_rcp<MODE>(dt, P.rt_h, P.rt_l);
+    rev_p = times_rcp<MODE>((float)nph, P.rp_h, P.rp_l);
   }
 }
 
@@ -259,7 +268,7 @@ VC_DI float dot_pair(uint64_t wa, uint64_t wb, const Params& P)
   level_revs<MODE>(ta, pa, P, rta, rpa);
   level_revs<MODE>(tb, pb, P, rtb, rpb);
   if (MODE == PLAIN || MODE == FRAC || ((MODE == TANH || MODE == COS) && !P.comp_t))
-    drev = times_dd((float)((int)ta - (int)tb), P.rt_h, P.rt_l);   // |ta - tb| < 2^24: exact
+    drev = times_rcp<MODE>((float)((int)ta - (int)tb), P.rt_h, P.rt_l);   // |ta - tb| < 2^24: exact
   else
     drev = rta - rtb;
   const float sa = sin_rev(rpa), ca = cos_rev(rpa), sb = sin_rev(rpb), cb = cos_rev(rpb);

@@ -109,6 +109,14 @@ def test_emulated_dot_pair_matches_oracle(layout, mode, kw):
     assert np.all(np.abs(got - ref) <= 1e-6 * scale), np.max(np.abs(got - ref) / np.maximum(scale, 1e-300))
 
 
+def test_single_product_level_reciprocals():
+    """Uniform levels have n_max = 2^k - 1 (k = 16..18), whose reciprocal (and half of it) rounds
+    to float32 within 2^-32 relative, so the decode's single product loses nothing measurable."""
+    for k in (16, 17, 18):
+        for r in (1.0 / ((1 << k) - 1), 1.0 / (2.0 * ((1 << k) - 1))):
+            assert abs(float(np.float32(r)) - r) / r <= 2.0 ** -32
+
+
 def test_emulated_exact_norm_path():
     """The exact integer magnitude path (taken near rounding midpoints) is exact."""
     g = np.random.default_rng(10)
