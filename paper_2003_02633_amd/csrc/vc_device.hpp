@@ -212,7 +212,12 @@ VC_DI float times_rcp(float x, float h, float l)
 template <int MODE>
 VC_DI void level_revs(uint32_t nth, uint32_t nph, const Params& P, float& rev_t, float& rev_p)
 {
-  const float dt = (float)nth - P.half_t;                 // exact
+  // theta: (n - n_max/2)/n_max = n/n_max - 1/2, one FMA with the single-product reciprocal;
+  // the fractional split forms n - n_max/2 exactly and takes the double-float reciprocal
+  auto theta_rev = [&]() {
+    if (MODE == FRAC) return times_rcp<MODE>((float)nth - P.half_t, P.rt_h, P.rt_l);
+    return fma_((float)nth, P.rt_h, -0.5f);
+  };
   if (MODE == TANH || MODE == COS) {
     const float hh_t = (2.0f * (float)nth - (float)P.nmax_t) / (float)P.nmax_t;
     const float hh_p = (2.0f * (float)nph - (float)P.nmax_p) / (float)P.nmax_p;
@@ -228,10 +233,10 @@ VC_DI void level_revs(uint32_t nth, uint32_t nph, const Params& P, float& rev_t,
     }
     rev_t = 0.5f * ut;
     rev_p = 0.25f * (up + 1.0f);
-    if (!P.comp_t) rev_t = times_rcp<MODE>(dt, P.rt_h, P.rt_l);
+    if (!P.comp_t) rev_t = theta_rev();
     if (!P.comp_p) rev_p = times_rcp<MODE>((float)nph, P.rp_h, P.rp_l);
   } else {
-    rev_t = times_rcp<MODE>(dt, P.rt_h, P.rt_l);
+    rev_t = theta_rev();
     rev_p = times_rcp<MODE>((float)nph, P.rp_h, P.rp_l);
   }
 }
@@ -664,8 +669,8 @@ VC_DI uint64_t encode_vec64(float x, float y, float z, const Params& P)
   const double S = fma64_(Z, Z, R2);              // r^2, two roundings (2^-52)
   // a finite float squares to below 2^256, so S is finite exactly when every component is; the
   // squares of nonzero floats are normal doubles, so S is zero only for the zero vector
-  if (!(S < __builtin_huge_val())) return L::reserved;   // non-finite input
-  if (S == 0.0) return 0ull;                      // zero vector
+  if (!(S > 0.0 && S < __builtin_huge_val()))    // one test for both special cases:
+    return S == 0.0 ? 0ull : L::reserved;         // the zero vector, non-finite input
 
   // ---- magnitude: r to ~2^-47 (rsqrt seed + one Newton step), nearest-even at 1+m bits
   const double yS = rsq64_(S);
