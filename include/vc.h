@@ -62,7 +62,10 @@ typedef enum {
 typedef enum { VC_MODE_PLAIN = 0, VC_MODE_TANH = 1, VC_MODE_COS = 2, VC_MODE_FRACSPLIT = 3 } vc_mode;
 
 /* magnitude rounding: nearest-even of the exact norm (default), or the paper-literal
- * truncation of the single-precision magnitude's trailing mantissa bits (§2.3) */
+ * truncation of the single-precision magnitude's trailing mantissa bits (§2.3): the norm
+ * rounded to nearest-even at 24 bits, then its low 23 - m mantissa bits dropped.  With a
+ * 23-bit mantissa nothing is dropped and the two give the same codes.  Decoding does not
+ * depend on it. */
 typedef enum { VC_MAG_RNE = 0, VC_MAG_TRUNC = 1 } vc_mag_round;
 
 enum { VC_COMPAND_PHI = 1, VC_COMPAND_THETA = 2 };

@@ -13,9 +13,10 @@
  *     uint64_t w = vc_inline::encode(p, x, y, z);            // Eq. (a_disc), §2.3 magnitude
  *     vc_inline::decode(p, w, x, y, z);                      // Eq. (a_inv), Eq. (cart2sphere)
  *     float d = vc_inline::dot(p, wa, wb);                   // decode(wa) . decode(wb)
- * The template arguments select the layout (vc_inline::L0722, L0723, L0823, L1823), the mode
- * (PLAIN, TANH, COS, FRAC) and the encoder precision (PREC_F64, PREC_F32); they must match the
- * codec given to vcx_inline_params (the defaults match vc_codec_init's defaults).  The results
+ * The template arguments select the layout (vc_inline::L0722, L0723, L0823, L1823; L0722T for
+ * the <0,7,22> layout with VC_MAG_TRUNC, where the other layouts' truncation equals nearest-even),
+ * the mode (PLAIN, TANH, COS, FRAC) and the encoder precision (PREC_F64, PREC_F32); they must
+ * match the codec given to vcx_inline_params (the defaults match vc_codec_init's defaults).  The results
  * are those of the library's own kernels, bit for bit: both compile the same functions.
  *
  * Build user kernels with hipcc --offload-arch=gfx950 -Xclang -target-feature -Xclang
@@ -34,6 +35,7 @@ using L0722 = vc::L0722;
 using L0723 = vc::L0723;
 using L0823 = vc::L0823;
 using L1823 = vc::L1823;
+using L0722T = vc::L0722T;   // <0,7,22>-17-18 with the truncating magnitude (VC_MAG_TRUNC)
 constexpr int PLAIN = vc::PLAIN, TANH = vc::TANH, COS = vc::COS, FRAC = vc::FRAC;
 constexpr int PREC_F32 = vc::PREC_F32, PREC_F64 = vc::PREC_F64;
 

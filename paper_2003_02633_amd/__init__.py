@@ -106,11 +106,12 @@ PRECISIONS = {"f64": 0, "f32": 1}
 
 
 def codec(layout: str = "0,7,22-17-18", mode: str = "plain", gamma: float = 0.5, P: int = 1 << 17,
-          compand: str = "both", precision: str = "f64") -> vc_codec:
+          compand: str = "both", precision: str = "f64", mag_round: str = "rne") -> vc_codec:
     c = vc_codec()
     _check(lib().vc_codec_init(C.byref(c), layout.encode()), "vc_codec_init")
     c.precision = PRECISIONS[precision]
     c.mode = MODES[mode]
+    c.mag_round = {"rne": 0, "trunc": 1}[mag_round]
     c.gamma = float(gamma)
     c.frac_P = int(P)
     c.compand_mask = {"both": 3, "phi": 1, "theta": 2, "none": 0}[compand]

@@ -21,6 +21,8 @@
 //     (pairs of FP32) arithmetic; the level coordinate is exact to ~2^-24 level units, and
 //     norms within 2^-14 grid units of a midpoint (about 3 in 10^5) take the exact path.
 // In both, the half-up ties of the axis directions (theta = 0, phi = pi/2) come out exactly.
+// A layout with the truncating magnitude (L0722T) instead rounds the norm to nearest-even at
+// 24 bits, the float32 magnitude, and drops its trailing 23 - m mantissa bits (§2.3 as printed).
 // Decode: hardware sin/cos in revolutions (v_sin_f32 / v_cos_f32) of an exactly formed level
 // offset, accuracy ~3e-7 of |x|; the dot product of two codes is taken in spherical form.
 //
@@ -99,10 +101,14 @@ VC_DI uint32_t umax3(uint32_t a, uint32_t b, uint32_t c) { uint32_t m = a > b ? 
 
 // ------------------------------------------------------------------ layouts
 // <S,E,M>-P-T with exponent bias BIAS; fields MSB->LSB: sign, exponent,
-// mantissa, n_phi, n_theta (Fig. comp_regimes).
-template <int S_, int E_, int M_, int P_, int T_, int BIAS_>
+// mantissa, n_phi, n_theta (Fig. comp_regimes).  TR selects the magnitude rounding of the
+// encoder: 0 nearest-even from the exact norm at 1+M bits, 1 the float32 magnitude (nearest-even
+// at 24 bits) with its trailing 23 - M bits dropped.  Decoding does not depend on it.
+template <int S_, int E_, int M_, int P_, int T_, int BIAS_, int TR_ = 0>
 struct Layout {
   static constexpr int s = S_, e = E_, m = M_, p = P_, t = T_, bias = BIAS_;
+  static constexpr bool trunc = TR_ != 0;
+  static constexpr int mr = trunc ? 23 : M_;          // fraction bits the norm is rounded to
   static constexpr int sh_p = T_, sh_m = T_ + P_, sh_e = T_ + P_ + M_;
   static constexpr uint32_t emask = (1u << E_) - 1u;
   static constexpr int emax = (int)emask - 1;         // all-ones exponent is reserved
@@ -112,8 +118,10 @@ struct Layout {
   static constexpr uint64_t saturated = ((uint64_t)(emask - 1u) << sh_e) | (((1ull << M_) - 1ull) << sh_m);
   static_assert(S_ + E_ + M_ + P_ + T_ == 64, "layout must fill 64 bits");
   static_assert(M_ == 22 || M_ == 23, "mantissa of 22 or 23 bits");
+  static_assert(!TR_ || (M_ < 23 && !keep_sub), "truncation drops bits only below 23; no subnormal codes");
 };
 using L0722 = Layout<0, 7, 22, 17, 18, 80>;
+using L0722T = Layout<0, 7, 22, 17, 18, 80, 1>;     // <0,7,22>-17-18, truncating magnitude
 using L0723 = Layout<0, 7, 23, 17, 17, 80>;
 using L0823 = Layout<0, 8, 23, 16, 17, 127>;
 using L1823 = Layout<1, 8, 23, 16, 16, 127>;
@@ -499,12 +507,12 @@ VC_DI uint64_t encode_vec32(float x, float y, float z, const Params& P)
   const float bb = Sh - r2h;
   const float Sl = ((r2h - (Sh - bb)) + (pz - bb)) + (r2l + ez);
 
-  // ---- magnitude: r = sqrt(S) as r0 + rlo, then nearest-even at 1+m bits
+  // ---- magnitude: r = sqrt(S) as r0 + rlo, then nearest-even at 1+mr bits
   const float rS = rsq_(Sh);
   const float r0 = Sh * rS;
   const float rlo = (fma_(-r0, r0, Sh) + Sl) * (0.5f * rS);
   const uint32_t b0 = fbits(r0);
-  constexpr int drop = 23 - L::m;                 // grid step in ulps of r0 is 2^drop
+  constexpr int drop = 23 - L::mr;                // grid step in ulps of r0 is 2^drop
   constexpr uint32_t lowm = (1u << drop) - 1u;
   const float v = ldexp_(rlo, 150 - (int)(b0 >> 23));   // rlo in ulps of r0
   const float pg = ((float)(b0 & lowm) + v) * (1.0f / (float)(1u << drop));
@@ -515,12 +523,13 @@ VC_DI uint64_t encode_vec32(float x, float y, float z, const Params& P)
   const int jg = (int)fl + (fr > 0.5f ? 1 : 0);
   uint32_t rb = (b0 & ~lowm) + ((uint32_t)jg << drop);
   int e_r = (int)(rb >> 23) - 127 + k;            // unbiased exponent of r_hat
-  uint32_t Mfield = (rb & 0x7fffffu) >> drop;
+  uint32_t Mfield = (rb & 0x7fffffu) >> (23 - L::m);   // truncating: the low 23 - m bits drop
   if (L::keep_sub) amb = amb || (e_r + L::bias <= 1);
   if (amb) {
     uint32_t j;
     int g;
-    exact_norm_round(x, y, z, L::m + 1, L::keep_sub, j, g);
+    exact_norm_round(x, y, z, L::mr + 1, L::keep_sub, j, g);
+    if constexpr (L::trunc) { j >>= L::mr - L::m; g += L::mr - L::m; }
     if (j >= (1u << L::m)) {                      // normal
       e_r = g + L::m;
       Mfield = j - (1u << L::m);
@@ -672,16 +681,17 @@ VC_DI uint64_t encode_vec64(float x, float y, float z, const Params& P)
   if (!(S > 0.0 && S < __builtin_huge_val()))    // one test for both special cases:
     return S == 0.0 ? 0ull : L::reserved;         // the zero vector, non-finite input
 
-  // ---- magnitude: r to ~2^-47 (rsqrt seed + one Newton step), nearest-even at 1+m bits
+  // ---- magnitude: r to ~2^-47 (rsqrt seed + one Newton step), nearest-even at 1+mr bits
   const double yS = rsq64_(S);
   const double r0 = S * yS;
   const double r = fma64_(fma64_(-r0, r0, S), 0.5 * yS, r0);
-  constexpr int drop = 52 - L::m;                 // fraction bits dropped from the FP64 value
+  constexpr int drop = 52 - L::mr;                // fraction bits dropped from the FP64 value
   constexpr uint32_t half = 1u << (drop - 1);
   const uint64_t rb0 = dbits(r);
   const uint32_t low = (uint32_t)rb0 & ((1u << drop) - 1u);
   bool amb = (low - (half - 256u)) < 512u;        // within 2^-44 of a rounding midpoint
-  const uint64_t rb = (rb0 + half) & ~((1ull << drop) - 1ull);
+  // rounded, then (truncating layouts) the fraction bits below m dropped
+  const uint64_t rb = (rb0 + half) & ~((1ull << (52 - L::m)) - 1ull);
   // code exponent E = e + bias lies in [1, emax]  <=>  rb in [rb_lo, rb_hi)
   constexpr uint64_t rb_lo = (uint64_t)(1024 - L::bias) << 52;
   constexpr uint64_t rb_hi = (uint64_t)(1024 - L::bias + L::emax) << 52;
@@ -698,7 +708,8 @@ VC_DI uint64_t encode_vec64(float x, float y, float z, const Params& P)
     uint32_t j;
     int g, e_r;
     uint32_t Mfield;
-    exact_norm_round(x, y, z, L::m + 1, L::keep_sub, j, g);
+    exact_norm_round(x, y, z, L::mr + 1, L::keep_sub, j, g);
+    if constexpr (L::trunc) { j >>= L::mr - L::m; g += L::mr - L::m; }
     if (j >= (1u << L::m)) { e_r = g + L::m; Mfield = j - (1u << L::m); }
     else { e_r = -L::bias; Mfield = j; }
     int E = e_r + L::bias;

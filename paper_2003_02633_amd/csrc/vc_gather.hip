@@ -103,7 +103,7 @@ extern "C" vc_status vc_gather_decode(const vc_codec* c, const uint64_t* codes, 
   if ((!codes && n_src) || !idx || !out) return VC_ERROR_INVALID_VALUE;
   if (((uintptr_t)codes & 7u) || ((uintptr_t)idx & 3u) || ((uintptr_t)out & 3u)) return VC_ERROR_MISALIGNED;
   if (overlap(out, 12 * n, codes, 8 * n_src) || overlap(out, 12 * n, idx, 4 * n)) return VC_ERROR_OVERLAP;
-  VC_DISPATCH(R, gather_t, R, codes, n_src, idx, n, out, stream);
+  VC_DISPATCH_NOPREC(R, gather_t, R, codes, n_src, idx, n, out, stream);
 }
 
 extern "C" vc_status vc_scatter_encode(const vc_codec* c, const float* xyz, const uint32_t* idx, size_t n,

@@ -38,7 +38,8 @@ inline vc_status launch_status()
   return e == hipSuccess ? VC_SUCCESS : VC_ERROR_LAUNCH;
 }
 
-// layout x mode x precision dispatch (decode-only paths ignore the precision)
+// layout x mode x precision dispatch (decode-only paths ignore the precision and the
+// magnitude rounding); the truncating magnitude of the 22-bit mantissa is keys 16-19
 #define VC_CASES(FN, PR, ...)                                                             \
   case 0: return FN<L0722, PLAIN, PR>(__VA_ARGS__);                                       \
   case 1: return FN<L0722, TANH, PR>(__VA_ARGS__);                                        \
@@ -47,16 +48,24 @@ inline vc_status launch_status()
   case 4: return FN<L0723, PLAIN, PR>(__VA_ARGS__);                                       \
   case 8: return FN<L0823, PLAIN, PR>(__VA_ARGS__);                                       \
   case 12: return FN<L1823, PLAIN, PR>(__VA_ARGS__);
+#define VC_CASES_TRUNC(FN, PR, ...)                                                       \
+  case 16: return FN<L0722T, PLAIN, PR>(__VA_ARGS__);                                     \
+  case 17: return FN<L0722T, TANH, PR>(__VA_ARGS__);                                      \
+  case 18: return FN<L0722T, COS, PR>(__VA_ARGS__);                                       \
+  case 19: return FN<L0722T, FRAC, PR>(__VA_ARGS__);
+#define VC_ENC_KEY(R) ((R).layout * 4 + (R).mode + ((R).mag_round == VC_MAG_TRUNC ? 16 : 0))
 #define VC_DISPATCH(R, FN, ...)                                                           \
   do {                                                                                    \
     if ((R).prec == PREC_F64) {                                                           \
-      switch ((R).layout * 4 + (R).mode) {                                                \
+      switch (VC_ENC_KEY(R)) {                                                            \
         VC_CASES(FN, PREC_F64, __VA_ARGS__)                                               \
+        VC_CASES_TRUNC(FN, PREC_F64, __VA_ARGS__)                                         \
         default: return VC_ERROR_UNSUPPORTED_CODEC;                                       \
       }                                                                                   \
     } else {                                                                              \
-      switch ((R).layout * 4 + (R).mode) {                                                \
+      switch (VC_ENC_KEY(R)) {                                                            \
         VC_CASES(FN, PREC_F32, __VA_ARGS__)                                               \
+        VC_CASES_TRUNC(FN, PREC_F32, __VA_ARGS__)                                         \
         default: return VC_ERROR_UNSUPPORTED_CODEC;                                       \
       }                                                                                   \
     }                                                                                     \

@@ -163,7 +163,7 @@ inline vc_status resolve(const vc_codec* c, Resolved* R)
   if (c->struct_size != sizeof(vc_codec)) return VC_ERROR_INVALID_VALUE;
   if (c->layout > VC_LAYOUT_1_8_23_16_16) return VC_ERROR_UNSUPPORTED_CODEC;
   if (c->mode > VC_MODE_FRACSPLIT) return VC_ERROR_UNSUPPORTED_CODEC;
-  if (c->mag_round != VC_MAG_RNE) return VC_ERROR_UNSUPPORTED_CODEC;   // truncation: oracle-only
+  if (c->mag_round > VC_MAG_TRUNC) return VC_ERROR_UNSUPPORTED_CODEC;
   if (c->precision > VC_PREC_F32 || c->reserved0 != 0) return VC_ERROR_INVALID_VALUE;
   if (c->mode != VC_MODE_PLAIN && c->layout != VC_LAYOUT_0_7_22_17_18) return VC_ERROR_UNSUPPORTED_CODEC;
   // the single-precision encoder's companded level near the phi poles cancels to ~2^-24 of
@@ -173,7 +173,11 @@ inline vc_status resolve(const vc_codec* c, Resolved* R)
   memset(R, 0, sizeof(*R));
   R->layout = (int)c->layout;
   R->mode = (int)c->mode;
-  R->mag_round = (int)c->mag_round;
+  // with a 23-bit mantissa the truncation drops no bits: the magnitude is the float32 norm, which
+  // nearest-even at 24 bits gives as well (on the float32 subnormal grid where the layout keeps
+  // subnormals; a float32 overflow and an exponent above the field's both saturate)
+  R->mag_round = (c->mag_round == VC_MAG_TRUNC && layout_bits((int)c->layout).m < 23) ? VC_MAG_TRUNC
+                                                                                      : VC_MAG_RNE;
   R->prec = c->precision == VC_PREC_F32 ? PREC_F32 : PREC_F64;
   Params& P = R->P;
   const LayoutBits lb = layout_bits((int)c->layout);

@@ -31,7 +31,7 @@ static void dotp(const Params& P, const uint64_t* a, const uint64_t* b, float* o
 }
 
 #define EMU_DISPATCH(R, FN, ...)                      \
-  switch ((R).layout * 4 + (R).mode) {                \
+  switch ((R).layout * 4 + (R).mode + ((R).mag_round == VC_MAG_TRUNC ? 16 : 0)) { \
     case 0: FN<L0722, PLAIN>(__VA_ARGS__); break;     \
     case 1: FN<L0722, TANH>(__VA_ARGS__); break;      \
     case 2: FN<L0722, COS>(__VA_ARGS__); break;       \
@@ -39,6 +39,10 @@ static void dotp(const Params& P, const uint64_t* a, const uint64_t* b, float* o
     case 4: FN<L0723, PLAIN>(__VA_ARGS__); break;     \
     case 8: FN<L0823, PLAIN>(__VA_ARGS__); break;     \
     case 12: FN<L1823, PLAIN>(__VA_ARGS__); break;    \
+    case 16: FN<L0722T, PLAIN>(__VA_ARGS__); break;   \
+    case 17: FN<L0722T, TANH>(__VA_ARGS__); break;    \
+    case 18: FN<L0722T, COS>(__VA_ARGS__); break;     \
+    case 19: FN<L0722T, FRAC>(__VA_ARGS__); break;    \
     default: return VC_ERROR_UNSUPPORTED_CODEC;       \
   }
 

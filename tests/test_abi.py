@@ -88,6 +88,17 @@ def test_validation_errors_without_device_work(lib):
     assert lib.vc_axpy(C.byref(bad), 1.0, _fake(0x10000), _fake(0x20000), _fake(0x30000), n, None) == 3
     bad = vc.codec("0,8,23-16-17", mode="tanh")
     assert lib.vc_encode(C.byref(bad), _fake(0x10000), _fake(0x20000), n, None) == 3
+    bad = vc.codec()
+    bad.mag_round = 2                                  # no such magnitude rounding
+    assert lib.vc_encode(C.byref(bad), _fake(0x10000), _fake(0x20000), n, None) == 3
+    # the truncating magnitude is accepted with every layout, mode and encoder precision
+    # (validation only: n == 0)
+    for layout in ("0,7,22-17-18", "0,7,23-17-17", "0,8,23-16-17", "1,8,23-16-16"):
+        for prec in ("f64", "f32"):
+            ok = vc.codec(layout, precision=prec, mag_round="trunc")
+            assert lib.vc_encode(C.byref(ok), None, None, 0, None) == 0
+    ok = vc.codec(mode="frac", P=163840, mag_round="trunc")
+    assert lib.vc_axpy(C.byref(ok), 1.0, None, None, None, 0, None) == 0
     # reductions need an output
     assert lib.vc_dot(P, _fake(0x10000), _fake(0x20000), n, None, None) == 1
     # baselines

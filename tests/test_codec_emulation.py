@@ -38,6 +38,13 @@ for _prec in ("f64", "f32"):
         pytest.param("0,7,22-17-18", "tanh", {"gamma": 1.0, "precision": _prec}, marks=_m),
         pytest.param("0,7,22-17-18", "cos", {"precision": _prec}, marks=_m),
     ]
+    # the paper-literal truncating magnitude (§2.3); only the 22-bit mantissa drops a bit
+    VARIANTS += [
+        ("0,7,22-17-18", "plain", {"precision": _prec, "mag_round": "trunc"}),
+        ("0,7,22-17-18", "frac", {"P": 163840, "precision": _prec, "mag_round": "trunc"}),
+        pytest.param("0,7,22-17-18", "tanh", {"gamma": 0.5, "precision": _prec, "mag_round": "trunc"}, marks=_m),
+        ("0,8,23-16-17", "plain", {"precision": _prec, "mag_round": "trunc"}),
+    ]
 
 
 def _pair(layout, mode, kw):
@@ -70,7 +77,25 @@ def _workloads():
                                               dtype=np.float32)])
     return [("gauss", inputs.gaussian_with_edges(20000, 0)), ("sphere_log", inputs.sphere_loguniform(60000, 1)),
             ("crafted", crafted), ("tiny", tiny), ("vmf_pole", inputs.vmf(20000, 1000.0, seed=5)),
-            ("limits", limits)]
+            ("limits", limits), ("ties24", _ties24())]
+
+
+def _ties24():
+    """vectors whose norm is an odd 25-bit integer (times a power of two): exact ties of the
+    nearest-even rounding at 24 bits, from Pythagorean triples (m^2 - n^2, 2mn, m^2 + n^2)"""
+    out = []
+    for m in range(4096, 5793, 29):
+        n0 = math.isqrt(max(m * m - (1 << 24), 0)) + 1
+        for n in range(n0, n0 + 4):
+            a, b, c = m * m - n * n, 2 * m * n, m * m + n * n
+            if (m - n) % 2 == 0 or not (1 << 24) <= c < (1 << 25) or a >= (1 << 24) or b >= (1 << 24):
+                continue
+            for e in (-60, -10, 0, 20):
+                s = 2.0 ** e
+                out += [(a * s, b * s, 0.0), (-b * s, 0.0, a * s), (0.0, a * s, -b * s)]
+    xyz = np.array(out, dtype=np.float32)
+    assert np.array_equal(xyz.astype(np.float64), np.array(out))   # exactly representable
+    return xyz
 
 
 @pytest.mark.parametrize("layout,mode,kw", VARIANTS)
@@ -107,6 +132,34 @@ def test_emulated_dot_pair_matches_oracle(layout, mode, kw):
     scale = np.linalg.norm(A, axis=1) * np.linalg.norm(B, axis=1)
     assert np.all(got[50:60] == 0.0)
     assert np.all(np.abs(got - ref) <= 1e-6 * scale), np.max(np.abs(got - ref) / np.maximum(scale, 1e-300))
+
+
+def test_ties24_are_ties():
+    """the tie workload holds exact midpoints of the 24-bit rounding (checked in exact arithmetic)"""
+    xyz = _ties24()
+    assert len(xyz) > 50
+    for x, y, z in xyz[::7]:
+        S = exact_sq_norm(float(x), float(y), float(z))
+        r = Fraction(math.isqrt(S.numerator), math.isqrt(S.denominator))
+        assert r * r == S
+        e = math.floor(math.log2(r))
+        q = r / Fraction(2) ** (e - 24)          # 25 significant bits, odd last bit
+        assert q.denominator == 1 and q.numerator % 2 == 1
+
+
+def test_truncation_is_nearest_even_for_23bit_mantissas():
+    """the library resolves VC_MAG_TRUNC to nearest-even where the mantissa has 23 bits, since
+    no bit is dropped; the oracle's paper-literal truncation gives the same codes there"""
+    xs = np.concatenate([w for _, w in _workloads()])
+    for layout in ("0,7,23-17-17", "0,8,23-16-17", "1,8,23-16-16"):
+        ct, cr = O.codec(layout, mag_round="trunc"), O.codec(layout)
+        assert np.array_equal(O.encode(ct, xs), O.encode(cr, xs)), layout
+    # the 22-bit mantissa does differ: in units of its grid step, with r in [k, k + 1), nearest-even
+    # gives k + 1 above k + 1/2 and truncation only from k + 3/4 (where the 24-bit rounding
+    # carries), so a quarter of the norms land on different codes
+    ct, cr = O.codec(mag_round="trunc"), O.codec()
+    d = O.encode(ct, xs) != O.encode(cr, xs)
+    assert 0.2 < d.mean() < 0.3
 
 
 def test_single_product_level_reciprocals():

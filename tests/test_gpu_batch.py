@@ -182,11 +182,12 @@ def test_batch_in_place_axpy(torch_dev):
     plan.close()
 
 
-def test_batch_variant_codec(torch_dev):
-    """fractional split codec through the persistent kernel"""
+@pytest.mark.parametrize("kw", [{"mode": "frac", "P": 163840}, {"mag_round": "trunc"}])
+def test_batch_variant_codec(torch_dev, kw):
+    """fractional split and truncating-magnitude codecs through the persistent kernel"""
     torch = torch_dev
-    say("case: batch frac P=163840")
-    c, co = vc.codec(mode="frac", P=163840), O.codec(mode="frac", P=163840)
+    say(f"case: batch {kw}")
+    c, co = vc.codec(**kw), O.codec(**kw)
     lengths, ops = [3000, 7001, 20000, 1], ["axpy", "encode", "dot", "norm2"]
     segs, host = build_segments(torch, co, lengths, ops)
     exp = expected_codes(torch, c, segs)

@@ -65,7 +65,8 @@ CODECS = [("0,7,22-17-18", "plain", {"precision": "f64"}),
           ("0,7,22-17-18", "tanh", {"gamma": 0.5, "precision": "f64"}),
           ("0,7,22-17-18", "cos", {"precision": "f64"}),
           ("0,8,23-16-17", "plain", {"precision": "f64"}),
-          ("1,8,23-16-16", "plain", {"precision": "f64"})]
+          ("1,8,23-16-16", "plain", {"precision": "f64"}),
+          ("0,7,22-17-18", "plain", {"precision": "f64", "mag_round": "trunc"})]
 
 
 @pytest.mark.parametrize("layout,mode,kw", CODECS)

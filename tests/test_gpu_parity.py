@@ -87,6 +87,11 @@ for _prec in ("f64", "f32"):
 VARIANTS += [("0,7,22-17-18", "tanh", {"gamma": 0.5, "precision": "f64"}),
              ("0,7,22-17-18", "tanh", {"gamma": 1.0, "precision": "f64"}),
              ("0,7,22-17-18", "cos", {"precision": "f64"})]
+# the paper-literal truncating magnitude (§2.3): float32 norm, trailing mantissa bit dropped
+VARIANTS += [("0,7,22-17-18", "plain", {"precision": p, "mag_round": "trunc"}) for p in ("f64", "f32")]
+VARIANTS += [("0,7,22-17-18", "frac", {"P": 163840, "precision": "f32", "mag_round": "trunc"}),
+             ("0,7,22-17-18", "tanh", {"gamma": 0.5, "precision": "f64", "mag_round": "trunc"}),
+             ("0,8,23-16-17", "plain", {"precision": "f64", "mag_round": "trunc"})]
 
 
 @pytest.mark.parametrize("layout,mode,kw", VARIANTS)
@@ -136,7 +141,7 @@ def _axpy_operands(n, seed_a, seed_b):
     return xa, xb
 
 
-def _check_axpy(torch, c, co, wa, wb, alpha, label):
+def _check_axpy(torch, c, co, wa, wb, alpha, label, mag_err=2.0 ** -23):
     ta, tb = up(torch, wa), up(torch, wb)
     out = vc.vc_axpy(c, alpha, ta, tb)
     out2, c32 = vc.vcx_axpy_dump(c, alpha, ta, tb)
@@ -157,7 +162,7 @@ def _check_axpy(torch, c, co, wa, wb, alpha, label):
     scale = alpha * np.linalg.norm(A64, axis=1) + np.linalg.norm(B64, axis=1)
     ok = (nrm > 2.0 ** -70) & (nrm < 1e14)
     nt, npm = O.nmax(co)
-    codec_bound = math.hypot(math.pi / nt, math.pi / (2 * npm)) + 2.0 ** -23
+    codec_bound = math.hypot(math.pi / nt, math.pi / (2 * npm)) + mag_err
     err = np.linalg.norm(got - c64, axis=1)[ok]
     allowed = codec_bound * nrm[ok] + (4 * 2.0 ** -24 + 1e-6) * scale[ok]
     say(f"{label}: max end-to-end err/allowed = {(err / allowed).max():.3f}")
@@ -181,6 +186,23 @@ def test_axpy_config1(torch_dev, prec):
     wa, wb = O.encode(co, xa), O.encode(co, xb)
     _check_axpy(torch_dev, c, co, wa, wb, 1.0, "axpy config1 alpha=1")
     _check_axpy(torch_dev, c, co, wa, wb, ALPHA, "axpy config1 alpha=0.7")
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_axpy_truncating_magnitude(torch_dev, prec):
+    """the paper-literal magnitude: nearest-even at 24 bits, the last of them dropped, so the
+    magnitude error is below 2^-22 + 2^-24 of the norm"""
+    say(f"case: axpy truncating magnitude {prec}")
+    c, co = vc.codec(precision=prec, mag_round="trunc"), O.codec(mag_round="trunc")
+    xa, xb = _axpy_operands(65536, 20, 21)
+    wa, wb = O.encode(co, xa), O.encode(co, xb)
+    _check_axpy(torch_dev, c, co, wa, wb, ALPHA, "axpy trunc alpha=0.7", mag_err=2.0 ** -22 + 2.0 ** -24)
+    # the codes differ from the nearest-even codec's on about a quarter of the sums
+    wr = down(vc.vc_axpy(vc.codec(precision=prec), ALPHA, up(torch_dev, wa), up(torch_dev, wb)), True)
+    wt = down(vc.vc_axpy(c, ALPHA, up(torch_dev, wa), up(torch_dev, wb)), True)
+    frac = float(np.mean(wr != wt))
+    say(f"axpy trunc vs rne: {frac * 100:.2f} % of codes differ")
+    assert 0.15 < frac < 0.35
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
