@@ -11,7 +11,7 @@ GOLDEN = os.path.join(ROOT, "tests", "golden")
 
 
 def pytest_configure(config):
-    config.addinivalue_line("markers", "gpu: needs an AMD MI355X GPU (run on the GPU box)")
+    config.addinivalue_line("markers", "gpu: needs an AMD MI355X GPU")
 
 
 def read_numbers(name="paper_numbers.txt"):

@@ -1,6 +1,6 @@
 """Code-level comparison of device (or emulated) codes with the oracle.
 
-Rule (spec contract): codes must equal the oracle's bit for bit, except
+Rule: codes must equal the oracle's bit for bit, except
 that an angle field may differ by exactly one level when the exact level
 coordinate lies within one single-precision ulp of the angle (expressed in
 level units) of the boundary between the two levels.  Such cases are counted.
