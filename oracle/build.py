@@ -14,7 +14,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 def build(verbose: bool = False) -> str:
     src = os.path.join(HERE, "vco.c")
-    tmp = LIB + ".tmp"
+    tmp = f"{LIB}.tmp{os.getpid()}"
     # IEEE semantics: no fast-math, no contraction of a*b+c into FMA
     cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
            "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wextra",

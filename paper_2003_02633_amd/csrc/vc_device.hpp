@@ -600,13 +600,15 @@ VC_DI uint64_t encode_vec32(float x, float y, float z, const Params& P)
 // ------------------------------------------------------------------ FP64-assisted encode
 // Same definitions, with the norm, the angle ratios and the level coordinates carried
 // in double precision (the paper's implementation section prescribes double-precision
-// intermediates for phi).  On gfx950 an FP64 FMA costs ~1.3 FP32 FMAs, so this is
+// intermediates for phi).  On gfx950 an FP64 FMA issues like an FP32 one, so this is
 // cheaper than the double-float single-precision path.  The hardware FP64
 // reciprocal/rsqrt are ~2^-24 accurate and get one correction step each.
 
 // Level coordinate of atan2(num, den), num, den >= 0: V = Kq atan2/(pi/2) (den >= 0),
 // 2 Kq - that (den < 0), with C = Kq/(pi/2), plus `add` (a multiple of 1/2).
-// mx = max(num, den), mn = min(num, den), swap = num > den.
+// mx = max(num, den), mn = min(num, den), swap = num > den.  POLE: mx may be zero (num = den =
+// 0); the denominator is then raised to 2^-1000, so the ratio is 0 and the angle atan2(0, 0) = 0.
+template <bool POLE = false>
 VC_DI double angle_levels64_mm(double mx, double mn, bool swap, bool den_neg, double Kq_half, double C,
                                double add = 0.0)
 {
@@ -616,7 +618,8 @@ VC_DI double angle_levels64_mm(double mx, double mn, bool swap, bool den_neg, do
   // or exact when the factor is 0)
   const double Rd = R ? 1.0 : 0.0;
   const double nu = fma64_(-Rd, mx, mn);
-  const double de = fma64_(Rd, mn, mx);           // > 0 except at the pole (caller fixes theta there)
+  double de = fma64_(Rd, mn, mx);                 // >= mx > 0 unless num = den = 0
+  if constexpr (POLE) de = __builtin_fmax(de, 0x1p-1000);
   const double rc = rcp64_(de);
   double b = nu * rc;
   b = fma64_(fma64_(-b, de, nu), rc, b);          // quotient to ~2^-48
@@ -637,7 +640,8 @@ VC_DI double angle_levels64_mm(double mx, double mn, bool swap, bool den_neg, do
 
 VC_DI double angle_levels64(double num, double den, bool den_neg, double Kq_half, double C, double add = 0.0)
 {
-  return angle_levels64_mm(__builtin_fmax(num, den), __builtin_fmin(num, den), num > den, den_neg, Kq_half, C, add);
+  return angle_levels64_mm<false>(__builtin_fmax(num, den), __builtin_fmin(num, den), num > den, den_neg, Kq_half, C,
+                                  add);
 }
 
 // Companded level distance from the centre: K h(q/K) for q = K |u| >= 0.
@@ -727,7 +731,8 @@ VC_DI uint64_t encode_vec64(float x, float y, float z, const Params& P)
 
   // ---- theta: |Q| = Kt |theta|/pi; n = base + floor(+-|Q| (+1/2 if n_theta_max is even))
   const bool yneg = y < 0.0f, xneg = x < 0.0f, zneg = z < 0.0f;
-  double Q = angle_levels64_mm(Mx, Mn, ay > ax, xneg, 0.25 * P.Kt64, P.Ct64);
+  // at the pole (x = y = 0) the angle is atan2(0, 0) = 0 and the level the base level (R12)
+  double Q = angle_levels64_mm<true>(Mx, Mn, ay > ax, xneg, 0.25 * P.Kt64, P.Ct64);
   if ((MODE == TANH || MODE == COS) && P.comp_t) Q = compand64<MODE>(Q, P.invKt64, P);
   uint32_t nth;
   if (MODE == FRAC) {
@@ -739,7 +744,6 @@ VC_DI uint64_t encode_vec64(float x, float y, float z, const Params& P)
     const int f = (int)Q;
     nth = yneg ? (uint32_t)((int)P.base_t - 1 - f) : (uint32_t)((int)P.base_t + f);
   }
-  if (R2 == 0.0) nth = P.base_t;                  // pole: theta = atan2(0, 0) = 0
 
   // ---- phi: V = n_phi_max phi/pi; n = floor(V + 1/2)
   uint32_t nph;

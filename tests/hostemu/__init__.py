@@ -18,10 +18,13 @@ def build():
                     for f in ("vc_device.hpp", "vc_params.hpp", "vc_coeffs.inc")]
     if os.path.exists(LIB) and all(os.path.getmtime(LIB) >= os.path.getmtime(d) for d in deps):
         return LIB
+    # a private temporary per process, then an atomic rename: parallel test workers may build at
+    # the same time, and each loads a complete library
+    tmp = f"{LIB}.tmp{os.getpid()}"
     cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",
-           "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", SRC, "-o", LIB + ".tmp"]
+           "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", SRC, "-o", tmp]
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
+    os.replace(tmp, LIB)
     return LIB
 
 

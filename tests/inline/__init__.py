@@ -18,11 +18,11 @@ def build():
     os.makedirs(OUT_DIR, exist_ok=True)
     libdir = os.path.join(ROOT, "paper_2003_02633_amd")
     cmd = [B.HIPCC, *B.COMMON, "-shared", SRC, "-L", libdir, "-lvc",
-           "-Wl,-rpath,$ORIGIN/../../../paper_2003_02633_amd", "-o", LIB + ".tmp"]
+           "-Wl,-rpath,$ORIGIN/../../../paper_2003_02633_amd", "-o", f"{LIB}.tmp{os.getpid()}"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed for the inline user kernel:\n" + r.stderr[-3000:])
-    os.replace(LIB + ".tmp", LIB)
+    os.replace(f"{LIB}.tmp{os.getpid()}", LIB)
     return LIB
 
 

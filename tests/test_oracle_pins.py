@@ -276,6 +276,43 @@ def _angles(v):
     return th, ph
 
 
+def test_angles_against_long_double_acos():
+    """phi cross-checked through the other closed form, phi = arccos(z / r), in x87 long double
+    (and theta through the long-double atan2): the oracle's pre-floor level coordinates agree to
+    1e-6 level units, and its levels are the floors of the long-double coordinates wherever
+    those are not within 1e-6 of a level boundary (§2.1, Eqs. cart2sphere and a_disc)"""
+    if np.finfo(np.longdouble).eps > 1e-18:
+        pytest.skip("long double is not wider than double on this platform")
+    c = O.codec()
+    xs = np.concatenate([inputs.sphere_loguniform(20000, 41), inputs.vmf(5000, 1000.0, seed=42),
+                         inputs.gaussian_with_edges(5000, 43)])
+    w, q5, flags = O.encode_detail(c, xs)
+    X = xs.astype(np.longdouble)
+    r = np.sqrt((X * X).sum(axis=1))
+    ok = (r > 0) & ((flags & 2) == 0)                     # flushed vectors carry no angles
+    X, r, w, q5 = X[ok], r[ok], w[ok], q5[ok]
+    pi = np.arctan2(np.longdouble(0), np.longdouble(-1))
+    nt, npm = O.nmax(c)
+    phi = np.arccos(X[:, 2] / r)
+    theta = np.arctan2(X[:, 1], X[:, 0])
+    Qp = npm * (phi / pi - np.longdouble(0.5))            # n_phi_max u_phi / 2, u_phi = 2 phi/pi - 1
+    Qt = nt * theta / (2 * pi)                             # n_theta_max u_theta / 2, u_theta = theta/pi
+    # arccos is ill-conditioned near the poles (error ~ eps / sin(phi)); compare where sin(phi)
+    # exceeds 1e-4 (all random draws) and at the exact poles, where arccos(+-1) is exact
+    sinphi = np.sqrt(X[:, 0] ** 2 + X[:, 1] ** 2) / r
+    keep = (sinphi > 1e-4) | (sinphi == 0)
+    assert keep.mean() > 0.999
+    Qp, Qt, w, q5 = Qp[keep], Qt[keep], w[keep], q5[keep]
+    assert np.abs(q5[:, 2] - Qp.astype(np.float64)).max() < 1e-6
+    assert np.abs(q5[:, 0] - Qt.astype(np.float64)).max() < 1e-6
+    _, _, P, T = O.fields(c, w)
+    for Q, n, base in ((Qp, P, (npm + 1) // 2), (Qt, T, (nt + 1) // 2)):
+        fl = np.floor(Q)
+        clear = np.minimum(Q - fl, fl + 1 - Q) > 1e-6
+        assert clear.mean() > 0.99
+        assert np.array_equal(n[clear].astype(np.int64), (base + fl[clear]).astype(np.int64))
+
+
 def test_angle_error_bounds():
     """Eq. (abs_e): |eps_theta| <= pi/n_theta_max, |eps_phi| <= pi/(2 n_phi_max)."""
     c = O.codec()
