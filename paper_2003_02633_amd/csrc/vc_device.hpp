@@ -89,6 +89,15 @@ VC_DI double rcp64_(double x) { return __builtin_amdgcn_rcp(x); }   // v_rcp_f64
 VC_DI double floor64_(double x) { return __builtin_floor(x); }
 VC_DI double fma64_(double a, double b, double c) { return __builtin_fma(a, b, c); }
 #endif
+// max / min of two doubles that are never NaN: the plain v_max_f64 / v_min_f64, without the
+// operand canonicalisation the compiler adds for fmax / fmin in IEEE mode
+#ifdef VC_HOST_EMULATION
+VC_DI double fmax64_nn(double a, double b) { return a > b ? a : b; }
+VC_DI double fmin64_nn(double a, double b) { return a < b ? a : b; }
+#else
+VC_DI double fmax64_nn(double a, double b) { double r; asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b)); return r; }
+VC_DI double fmin64_nn(double a, double b) { double r; asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b)); return r; }
+#endif
 VC_DI float fabs_(float x) { return ubits(fbits(x) & 0x7fffffffu); }
 #ifdef VC_HOST_EMULATION
 VC_DI float fmax_(float a, float b) { return fmaxf(a, b); }
@@ -640,8 +649,7 @@ VC_DI double angle_levels64_mm(double mx, double mn, bool swap, bool den_neg, do
 
 VC_DI double angle_levels64(double num, double den, bool den_neg, double Kq_half, double C, double add = 0.0)
 {
-  return angle_levels64_mm<false>(__builtin_fmax(num, den), __builtin_fmin(num, den), num > den, den_neg, Kq_half, C,
-                                  add);
+  return angle_levels64_mm<false>(fmax64_nn(num, den), fmin64_nn(num, den), num > den, den_neg, Kq_half, C, add);
 }
 
 // Companded level distance from the centre: K h(q/K) for q = K |u| >= 0.

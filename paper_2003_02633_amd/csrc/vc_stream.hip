@@ -30,23 +30,29 @@ __device__ __forceinline__ void st(T* p, T v)
 }
 
 // ------------------------------------------------------------------ axpy
-// Each lane handles U pairs of consecutive codes per grid step; pair u of a
-// block lives at [blk + u*2*BS + 2*tid, +2), so every load/store instruction of
-// a wave covers 1 KiB contiguous.
+// A tile is 2*BS*U consecutive codes.  Wave w of a block takes the U*128 codes from w*U*128 on:
+// in step u lane l handles the pair at w*U*128 + u*128 + 2l, so every load/store instruction of
+// a wave covers 1 KiB contiguous, and the steps of a lane are 1 KiB apart (immediate offsets of
+// one scalar base plus one per-lane byte offset).
 template <class L, int MODE, int PREC, int BS, int U, bool NT, bool DUMP>
 __global__ __launch_bounds__(BS) void k_axpy(const uint64_t* __restrict__ a, const uint64_t* __restrict__ b,
-                                             uint64_t* __restrict__ c, size_t n, size_t ntiles, float alpha,
+                                             uint64_t* __restrict__ c, size_t n, uint32_t ntiles, float alpha,
                                              Params P, float* __restrict__ dump)
 {
   // tiles [0, ntiles) take the 16-byte path (pointers 16-byte aligned); the rest is scalar
   constexpr size_t TILE = (size_t)2 * BS * U;
-  for (size_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const size_t base = tile * TILE + 2 * threadIdx.x;
+  const uint32_t first = (threadIdx.x >> 6) * (U * 128u) + 2u * (threadIdx.x & 63u);   // code index in a tile
+  const uint32_t off = 8u * first;                                                      // its byte offset
+  for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const size_t t0 = (size_t)tile * TILE;
+    const u64x2* pa = (const u64x2*)((const char*)(a + t0) + off);
+    const u64x2* pb = (const u64x2*)((const char*)(b + t0) + off);
+    u64x2* pc = (u64x2*)((char*)(c + t0) + off);
     u64x2 va[U], vb[U];
 #pragma unroll
     for (int u = 0; u < U; u++) {
-      va[u] = ld<NT>((const u64x2*)(a + base + (size_t)u * 2 * BS));
-      vb[u] = ld<NT>((const u64x2*)(b + base + (size_t)u * 2 * BS));
+      va[u] = ld<NT>(pa + 64 * u);
+      vb[u] = ld<NT>(pb + 64 * u);
     }
 #pragma unroll
     for (int u = 0; u < U; u++) {
@@ -60,16 +66,16 @@ __global__ __launch_bounds__(BS) void k_axpy(const uint64_t* __restrict__ a, con
         const float cy = __builtin_fmaf(alpha, ay, by);
         const float cz = __builtin_fmaf(alpha, az, bz);
         if constexpr (DUMP) {
-          const size_t i = base + (size_t)u * 2 * BS + h;
+          const size_t i = t0 + first + (size_t)u * 128 + h;
           dump[3 * i] = cx; dump[3 * i + 1] = cy; dump[3 * i + 2] = cz;
         }
         out[h] = encode_vec<L, MODE, PREC>(cx, cy, cz, P);
       }
-      st<NT>((u64x2*)(c + base + (size_t)u * 2 * BS), out);
+      st<NT>(pc + 64 * u, out);
     }
   }
   // tail: vectors from ntiles*TILE on, one per thread
-  const size_t start = ntiles * TILE;
+  const size_t start = (size_t)ntiles * TILE;
   for (size_t i = start + (size_t)blockIdx.x * BS + threadIdx.x; i < n; i += (size_t)gridDim.x * BS) {
     float ax, ay, az, bx, by, bz;
     decode_vec<L, MODE>(a[i], P, ax, ay, az);
@@ -256,14 +262,16 @@ static vc_status axpy_launch(const Resolved& R, float alpha, const uint64_t* a, 
 {
   constexpr size_t TILE = (size_t)2 * BS * U;
   const bool aligned = (((uintptr_t)a | (uintptr_t)b | (uintptr_t)c) & 15u) == 0;
-  const size_t ntiles = aligned ? n / TILE : 0;
+  // tiles are counted in 32 bits (2^32 tiles of at least 256 codes exceed any HBM); past that
+  // count the kernel's one-vector-per-lane tail would take the rest
+  const size_t ntiles = aligned ? (n / TILE < 0xffffffffu ? n / TILE : 0xffffffffu) : 0;
   const unsigned grid = grid_for(n, TILE, 1u << 30);
   if (dump)
-    hipLaunchKernelGGL((k_axpy<L, MODE, PREC, BS, U, false, true>), dim3(grid), dim3(BS), 0, s, a, b, c, n, ntiles,
-                       alpha, R.P, dump);
+    hipLaunchKernelGGL((k_axpy<L, MODE, PREC, BS, U, false, true>), dim3(grid), dim3(BS), 0, s, a, b, c, n,
+                       (uint32_t)ntiles, alpha, R.P, dump);
   else
-    hipLaunchKernelGGL((k_axpy<L, MODE, PREC, BS, U, NT, false>), dim3(grid), dim3(BS), 0, s, a, b, c, n, ntiles,
-                       alpha, R.P, dump);
+    hipLaunchKernelGGL((k_axpy<L, MODE, PREC, BS, U, NT, false>), dim3(grid), dim3(BS), 0, s, a, b, c, n,
+                       (uint32_t)ntiles, alpha, R.P, dump);
   return launch_status();
 }
 
