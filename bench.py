@@ -21,6 +21,7 @@ import argparse
 import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -127,6 +128,21 @@ def timed(torch, fn, steps: int, warmup) -> float:
     e1.record(s)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / steps
+
+
+def host_info(torch) -> dict:
+    """the machine the record comes from: CPU model, cores this process may use, GPU name"""
+    model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"cpu_model": model, "cores_available": cores, "gpu": torch.cuda.get_device_name(0)}
 
 
 def cpu_baseline(torch, wa_dev, wb_dev, target_s: float = 15.0):
@@ -407,7 +423,7 @@ def main():
     err = sample_error(torch, wa, wb, wc)
     log(f"sample error: {err}")
 
-    extras = {}
+    extras = {"host": host_info(torch)}
     if not args.quick:
         k = max(3, args.steps // 4)
         # uncompressed FP32 axpy over the same vectors (36 B/vec)

@@ -25,6 +25,14 @@
  *     all ones, other fields zero), which decodes to NaN.
  *   - The library never synchronises the device implicitly, except where
  *     documented (plan creation).
+ *
+ * Environment
+ *   VC_TUNE_CACHE  file of axpy launch configurations, applied on the first
+ *                  vc_axpy call (format in vc_ext.h, vcx_load_tuning).
+ *   VC_LOG         set to a non-empty value other than "0": vc_encode,
+ *                  vc_decode, vc_axpy, vcx_axpy_dump, vc_dot and vc_norm2 each
+ *                  write one line to stderr when they return (codec fields, n,
+ *                  the axpy launch configuration, the status).
  */
 #ifndef VC_H
 #define VC_H

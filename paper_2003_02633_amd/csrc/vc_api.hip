@@ -22,6 +22,36 @@ static bool overlaps(const void* p, size_t pb, const void* q, size_t qb)
   return a0 < b1 && b0 < a1;
 }
 
+// VC_LOG set to a non-empty value other than "0": each core entry point writes one line to stderr
+// when it returns (its codec, size, the axpy launch configuration, the status).  Read once.
+static bool log_on()
+{
+  static const bool on = [] {
+    const char* e = getenv("VC_LOG");
+    return e && *e && strcmp(e, "0") != 0;
+  }();
+  return on;
+}
+
+static vc_status logged(const char* fn, const vc_codec* c, size_t n, vc_status st)
+{
+  if (log_on()) {
+    char cfg[64] = "";
+    if (strcmp(fn, "vc_axpy") == 0 && c && c->struct_size == sizeof(vc_codec)) {
+      const StreamCfg g = stream_cfg(c->precision == VC_PREC_F32 ? PREC_F32 : PREC_F64);
+      const bool tuned = c->layout == VC_LAYOUT_0_7_22_17_18 && c->mode == VC_MODE_PLAIN && c->mag_round == VC_MAG_RNE;
+      snprintf(cfg, sizeof cfg, " block=%d pairs/lane=%d nt=%d", tuned ? g.block : 512, tuned ? g.vpt : 2,
+               tuned ? g.nt : 1);
+    }
+    if (c && c->struct_size == sizeof(vc_codec))
+      fprintf(stderr, "[vc] %s n=%zu layout=%u mode=%u mag_round=%u precision=%u%s -> %s\n", fn, n, c->layout,
+              c->mode, c->mag_round, c->precision, cfg, vc_status_string(st));
+    else
+      fprintf(stderr, "[vc] %s n=%zu (no valid codec) -> %s\n", fn, n, vc_status_string(st));
+  }
+  return st;
+}
+
 }  // namespace vc
 
 using namespace vc;
@@ -50,7 +80,7 @@ vc_status vc_codec_init(vc_codec* c, const char* layout)
   return VC_SUCCESS;
 }
 
-vc_status vc_encode(const vc_codec* c, const float* xyz, uint64_t* codes, size_t n, hipStream_t stream)
+static vc_status encode_impl(const vc_codec* c, const float* xyz, uint64_t* codes, size_t n, hipStream_t stream)
 {
   Resolved R;
   vc_status st = resolve(c, &R);
@@ -62,7 +92,12 @@ vc_status vc_encode(const vc_codec* c, const float* xyz, uint64_t* codes, size_t
   return launch_encode(R, xyz, codes, n, stream);
 }
 
-vc_status vc_decode(const vc_codec* c, const uint64_t* codes, float* xyz, size_t n, hipStream_t stream)
+vc_status vc_encode(const vc_codec* c, const float* xyz, uint64_t* codes, size_t n, hipStream_t stream)
+{
+  return logged("vc_encode", c, n, encode_impl(c, xyz, codes, n, stream));
+}
+
+static vc_status decode_impl(const vc_codec* c, const uint64_t* codes, float* xyz, size_t n, hipStream_t stream)
 {
   Resolved R;
   vc_status st = resolve(c, &R);
@@ -72,6 +107,11 @@ vc_status vc_decode(const vc_codec* c, const uint64_t* codes, float* xyz, size_t
   if (!aligned(xyz, 4) || !aligned(codes, 8)) return VC_ERROR_MISALIGNED;
   if (overlaps(xyz, 12 * n, codes, 8 * n)) return VC_ERROR_OVERLAP;
   return launch_decode(R, codes, xyz, n, stream);
+}
+
+vc_status vc_decode(const vc_codec* c, const uint64_t* codes, float* xyz, size_t n, hipStream_t stream)
+{
+  return logged("vc_decode", c, n, decode_impl(c, codes, xyz, n, stream));
 }
 
 static vc_status axpy_common(const vc_codec* c, float alpha, const uint64_t* a, const uint64_t* b, uint64_t* out,
@@ -149,14 +189,14 @@ vc_status vc_axpy(const vc_codec* c, float alpha, const uint64_t* a, const uint6
                   hipStream_t stream)
 {
   apply_env_tuning();
-  return axpy_common(c, alpha, a, b, out, n, nullptr, stream);
+  return logged("vc_axpy", c, n, axpy_common(c, alpha, a, b, out, n, nullptr, stream));
 }
 
 vc_status vcx_axpy_dump(const vc_codec* c, float alpha, const uint64_t* a, const uint64_t* b, uint64_t* out,
                         float* c32, size_t n, hipStream_t stream)
 {
   if (n && !c32) return VC_ERROR_INVALID_VALUE;
-  return axpy_common(c, alpha, a, b, out, n, c32, stream);
+  return logged("vcx_axpy_dump", c, n, axpy_common(c, alpha, a, b, out, n, c32, stream));
 }
 
 static vc_status reduce_common(const vc_codec* c, const uint64_t* a, const uint64_t* b, size_t n, float* d_out,
@@ -196,12 +236,12 @@ size_t vcx_inline_params_size(void) { return sizeof(Params); }
 vc_status vc_dot(const vc_codec* c, const uint64_t* a, const uint64_t* b, size_t n, float* d_out,
                  hipStream_t stream)
 {
-  return reduce_common(c, a, b, n, d_out, stream, true);
+  return logged("vc_dot", c, n, reduce_common(c, a, b, n, d_out, stream, true));
 }
 
 vc_status vc_norm2(const vc_codec* c, const uint64_t* a, size_t n, float* d_out, hipStream_t stream)
 {
-  return reduce_common(c, a, nullptr, n, d_out, stream, false);
+  return logged("vc_norm2", c, n, reduce_common(c, a, nullptr, n, d_out, stream, false));
 }
 
 const char* vc_status_string(vc_status s)

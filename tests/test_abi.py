@@ -237,3 +237,32 @@ def test_gather_scatter_validation_without_device_work(lib):
     assert lib.vc_scatter_encode(P, f(0x10000), f(0x20002), 8, f(0x30000), 8, None) == 2
     assert lib.vc_scatter_encode(P, f(0x10000), f(0x20000), 8, f(0x10000 + 16), 8, None) == 7
     assert lib.vcb_gather_f32(f(0x10000), 16, None, 8, f(0x30000), None) == 1
+
+
+def test_vc_log_lines_without_device_work():
+    """VC_LOG=1 makes each core entry point report its codec, size, launch configuration and
+    status on stderr; unset, nothing is written (validation-only calls, no GPU needed)"""
+    import subprocess
+    import sys
+    code = ("import ctypes as C, paper_2003_02633_amd as vc\n"
+            "L = vc.lib(); c = vc.codec(mag_round='trunc')\n"
+            "L.vc_encode(C.byref(c), None, None, 0, None)\n"
+            "L.vc_axpy(C.byref(vc.codec()), C.c_float(1.0), None, C.c_void_p(0x1000), C.c_void_p(0x2000), 16, None)\n"
+            "L.vc_norm2(C.byref(c), None, 0, None, None)\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    for val, expect in (("1", True), ("0", False), (None, False)):
+        env = {k: v for k, v in os.environ.items() if k != "VC_LOG"}
+        if val is not None:
+            env["VC_LOG"] = val
+        r = subprocess.run([sys.executable, "-c", code], cwd=root, env=env, capture_output=True, text=True,
+                           timeout=120)
+        assert r.returncode == 0, r.stderr
+        lines = [l for l in r.stderr.splitlines() if l.startswith("[vc] ")]
+        if not expect:
+            assert lines == []
+            continue
+        assert len(lines) == 3, r.stderr
+        assert lines[0] == "[vc] vc_encode n=0 layout=0 mode=0 mag_round=1 precision=0 -> VC_SUCCESS"
+        assert lines[1].startswith("[vc] vc_axpy n=16 layout=0 mode=0 mag_round=0 precision=0 block=")
+        assert lines[1].endswith("-> VC_ERROR_INVALID_VALUE")
+        assert lines[2].startswith("[vc] vc_norm2 n=0 ") and lines[2].endswith("-> VC_ERROR_INVALID_VALUE")   # needs d_out
