@@ -102,9 +102,16 @@ VC_DI float fabs_(float x) { return ubits(fbits(x) & 0x7fffffffu); }
 #ifdef VC_HOST_EMULATION
 VC_DI float fmax_(float a, float b) { return fmaxf(a, b); }
 VC_DI float fmin_(float a, float b) { return fminf(a, b); }
+// NaN-propagating maximum / minimum (IEEE 754-2019), unlike fmax / fmin, which drop a NaN
+VC_DI float fmaximum_(float a, float b) { return (a != a || b != b) ? NAN : fmaxf(a, b); }
+VC_DI float fminimum_(float a, float b) { return (a != a || b != b) ? NAN : fminf(a, b); }
 #else
 VC_DI float fmax_(float a, float b) { return __builtin_fmaxf(a, b); }
 VC_DI float fmin_(float a, float b) { return __builtin_fminf(a, b); }
+// NaN-propagating maximum / minimum (IEEE 754-2019; v_maximum3_f32 / v_minimum3_f32 on gfx950),
+// unlike fmax / fmin, which drop a NaN
+VC_DI float fmaximum_(float a, float b) { return __builtin_elementwise_maximum(a, b); }
+VC_DI float fminimum_(float a, float b) { return __builtin_elementwise_minimum(a, b); }
 #endif
 VC_DI uint32_t umax3(uint32_t a, uint32_t b, uint32_t c) { uint32_t m = a > b ? a : b; return m > c ? m : c; }
 
@@ -683,15 +690,19 @@ template <class L, int MODE>
 VC_DI uint64_t encode_vec64(float x, float y, float z, const Params& P)
 {
   // max and min of |x|, |y| (for theta's octant reduction) and |z|, taken in single precision and
-  // converted exactly; the squares are exact in FP64.  The signs come from the inputs below.
+  // converted exactly; the squares are exact in FP64.  The signs come from the inputs below.  The
+  // max and min propagate a NaN, so that a NaN in x or y reaches r^2 and the non-finite test.
   const float ax = __builtin_fabsf(x), ay = __builtin_fabsf(y);
-  const double Mx = (double)fmax_(ax, ay), Mn = (double)fmin_(ax, ay), Z = (double)__builtin_fabsf(z);
+  const double Mx = (double)fmaximum_(ax, ay), Mn = (double)fminimum_(ax, ay), Z = (double)__builtin_fabsf(z);
   const double R2 = fma64_(Mx, Mx, Mn * Mn);      // rho^2, one rounding
-  const double S = fma64_(Z, Z, R2);              // r^2, two roundings (2^-52)
-  // a finite float squares to below 2^256, so S is finite exactly when every component is; the
-  // squares of nonzero floats are normal doubles, so S is zero only for the zero vector
-  if (!(S > 0.0 && S < __builtin_huge_val()))    // one test for both special cases:
-    return S == 0.0 ? 0ull : L::reserved;         // the zero vector, non-finite input
+  // r^2, two roundings (2^-52).  A finite float squares to below 2^256, so r^2 is finite exactly
+  // when every component is.  The squares of nonzero floats are at least 2^-298, so raising r^2
+  // to 2^-1000 changes only the zero vector, whose norm 2^-500 then flushes to the zero code
+  // below like any norm under the smallest magnitude (through the exact path, where the layout
+  // keeps subnormals).
+  const double S0 = fma64_(Z, Z, R2);
+  if (!(S0 < __builtin_huge_val())) return L::reserved;  // non-finite input (the test is false for NaN)
+  const double S = fmax64_nn(S0, 0x1p-1000);
 
   // ---- magnitude: r to ~2^-47 (rsqrt seed + one Newton step), nearest-even at 1+mr bits
   const double yS = rsq64_(S);

@@ -77,7 +77,15 @@ def _workloads():
                                               dtype=np.float32)])
     return [("gauss", inputs.gaussian_with_edges(20000, 0)), ("sphere_log", inputs.sphere_loguniform(60000, 1)),
             ("crafted", crafted), ("tiny", tiny), ("vmf_pole", inputs.vmf(20000, 1000.0, seed=5)),
-            ("limits", limits), ("ties24", _ties24())]
+            ("limits", limits), ("ties24", _ties24()), ("nonfinite", _nonfinite())]
+
+
+def _nonfinite():
+    """every combination of NaN, +-inf, 0 and 1 in three components (the finite ones included):
+    non-finite input gives the reserved code, the zero vector the zero code"""
+    v = np.array([np.nan, np.inf, -np.inf, 0.0, -0.0, 1.0, 3e38], dtype=np.float32)
+    g = np.stack(np.meshgrid(v, v, v, indexing="ij"), axis=-1).reshape(-1, 3)
+    return np.ascontiguousarray(g)
 
 
 def _ties24():
@@ -105,8 +113,10 @@ def test_emulated_encode_matches_oracle(layout, mode, kw):
         dev = H.encode(c, xyz)
         res = classify(co, xyz, dev)
         assert res["other"] == 0, f"{name}:\n" + describe_bad(co, xyz, dev, res)
-        # within-window level differences are rare (design error ~1e-4 level units)
-        assert res["pm1_theta"] + res["pm1_phi"] <= max(2, 2e-3 * res["n"]), res
+        # within-window level differences are rare (design error ~1e-4 level units) on the drawn
+        # workloads; the non-finite grid is mostly axis and diagonal directions, on level ties
+        if name != "nonfinite":
+            assert res["pm1_theta"] + res["pm1_phi"] <= max(2, 2e-3 * res["n"]), res
 
 
 @pytest.mark.parametrize("layout,mode,kw", VARIANTS)

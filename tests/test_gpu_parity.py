@@ -114,6 +114,26 @@ def test_encode_decode_variants(torch_dev, layout, mode, kw):
         assert nan_ok and err <= 1e-6
 
 
+def test_encode_nonfinite_and_zero_grid(torch_dev):
+    """every combination of NaN, +-inf, +-0, 1 and 3e38 in three components, for every codec:
+    a NaN or infinity in any component gives the reserved code, the zero vector the zero code,
+    the rest the oracle's codes (within the window)"""
+    v = np.array([np.nan, np.inf, -np.inf, 0.0, -0.0, 1.0, 3e38], dtype=np.float32)
+    xyz = np.ascontiguousarray(np.stack(np.meshgrid(v, v, v, indexing="ij"), axis=-1).reshape(-1, 3))
+    bad = ~np.isfinite(xyz).all(axis=1)
+    zero = (xyz == 0).all(axis=1)
+    for layout, mode, kw in VARIANTS:
+        okw = {k: v for k, v in kw.items() if k != "precision"}
+        c, co = vc.codec(layout, mode=mode, **kw), O.codec(layout, mode=mode, **okw)
+        dev = gpu_encode(torch_dev, c, xyz)
+        ref = O.encode(co, xyz)
+        assert np.array_equal(dev[bad], ref[bad]) and len(set(ref[bad].tolist())) == 1, (layout, mode, kw)
+        assert (dev[zero] == 0).all(), (layout, mode, kw)
+        res = classify(co, xyz, dev)
+        assert res["other"] == 0, (layout, mode, kw, describe_bad(co, xyz, dev, res))
+    say(f"non-finite grid: {len(VARIANTS)} codecs, {int(bad.sum())} non-finite and {int(zero.sum())} zero vectors each")
+
+
 def test_decode_random_codes(torch_dev):
     """Every valid code (random fields) plus zero and reserved codes."""
     say("case: decode random codes")
