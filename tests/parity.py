@@ -74,3 +74,24 @@ def decode_err(co, codes, dev_xyz):
     rel = np.where(r > 0, err / np.where(r > 0, r, 1), err)
     nan_ok = np.array_equal(np.isnan(dev).any(axis=1), ~fin)
     return float(rel[fin].max(initial=0.0)), nan_ok
+
+
+def random_codes(n, seed):
+    """n arbitrary 64-bit codes (every field random: subnormal magnitudes of the e = 8 layouts,
+    reserved exponents, fractional-split fields beyond P T) plus the zero and all-ones words"""
+    g = np.random.default_rng(seed)
+    w = g.integers(0, 1 << 32, n, dtype=np.uint64) << np.uint64(32) | g.integers(0, 1 << 32, n, dtype=np.uint64)
+    w[:4] = [0, (1 << 64) - 1, 1 << 57, 127 << 57]
+    return w
+
+
+def decode_abs_err(co, w, dev):
+    """max over components of |x_dev - x_oracle| - (1e-6 r_hat + 2^-149): positive means out of
+    tolerance.  The float32 outputs of a subnormal-magnitude vector cannot be closer than the
+    subnormal spacing 2^-149, whatever r_hat is."""
+    ref = O.decode64(co, w)
+    dev = np.asarray(dev, dtype=np.float64).reshape(-1, 3)
+    fin = np.isfinite(ref).all(axis=1)
+    assert np.array_equal(np.isnan(dev).any(axis=1), ~fin)
+    r = np.linalg.norm(ref[fin], axis=1)
+    return float((np.abs(dev[fin] - ref[fin]).max(axis=1) - (1e-6 * r + 2.0 ** -149)).max(initial=-1.0))

@@ -15,7 +15,7 @@ import paper_2003_02633_amd as vc
 import tests.hostemu as H
 from paper_2003_02633_amd import inputs
 from tests.exact import exact_sq_norm, round_sqrt
-from tests.parity import classify, decode_err, describe_bad
+from tests.parity import classify, decode_abs_err, decode_err, describe_bad, random_codes
 
 from fractions import Fraction
 
@@ -125,6 +125,15 @@ def test_emulated_decode_matches_oracle(layout, mode, kw):
     w = O.encode(co, inputs.sphere_loguniform(50000, 2))
     err, nan_ok = decode_err(co, w, H.decode(c, w))
     assert nan_ok and err <= 1e-6
+
+
+@pytest.mark.parametrize("layout,mode,kw", VARIANTS)
+def test_emulated_decode_of_arbitrary_codes(layout, mode, kw):
+    """every 64-bit word decodes as the oracle decodes it: NaN exactly for the reserved exponent
+    (and fractional-split fields beyond the P T levels), values within 1e-6 r_hat + 2^-149"""
+    c, co = _pair(layout, mode, kw)
+    w = random_codes(200_000, 17)
+    assert decode_abs_err(co, w, H.decode(c, w)) <= 0.0
 
 
 @pytest.mark.parametrize("layout,mode,kw", [v for v in VARIANTS if not hasattr(v, "marks") or not v.marks])

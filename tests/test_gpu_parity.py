@@ -20,7 +20,7 @@ import pytest
 import oracle as O
 import paper_2003_02633_amd as vc
 from paper_2003_02633_amd import inputs
-from tests.parity import classify, decode_err, describe_bad
+from tests.parity import classify, decode_abs_err, decode_err, describe_bad, random_codes
 
 pytestmark = pytest.mark.gpu
 
@@ -134,6 +134,21 @@ def test_encode_nonfinite_and_zero_grid(torch_dev):
     say(f"non-finite grid: {len(VARIANTS)} codecs, {int(bad.sum())} non-finite and {int(zero.sum())} zero vectors each")
 
 
+def test_decode_arbitrary_codes_every_codec(torch_dev):
+    """every 64-bit word (subnormal magnitudes of the e = 8 layouts, reserved exponents,
+    fractional-split fields beyond P T) decodes as the oracle decodes it: NaN exactly where the
+    oracle gives NaN, values within 1e-6 r_hat + 2^-149"""
+    w = random_codes(1 << 18, 18)
+    for layout, mode, kw in VARIANTS:
+        okw = {k: v for k, v in kw.items() if k != "precision"}
+        c, co = vc.codec(layout, mode=mode, **kw), O.codec(layout, mode=mode, **okw)
+        d = vc.vc_decode(c, up(torch_dev, w))
+        torch_dev.cuda.synchronize()
+        excess = decode_abs_err(co, w, down(d))
+        assert excess <= 0.0, (layout, mode, kw, excess)
+    say(f"arbitrary codes: {len(VARIANTS)} codecs x {len(w)} words decode within tolerance")
+
+
 def test_decode_random_codes(torch_dev):
     """Every valid code (random fields) plus zero and reserved codes."""
     say("case: decode random codes")
@@ -206,6 +221,29 @@ def test_axpy_config1(torch_dev, prec):
     wa, wb = O.encode(co, xa), O.encode(co, xb)
     _check_axpy(torch_dev, c, co, wa, wb, 1.0, "axpy config1 alpha=1")
     _check_axpy(torch_dev, c, co, wa, wb, ALPHA, "axpy config1 alpha=0.7")
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_axpy_arbitrary_codes(torch_dev, prec):
+    """operands of arbitrary 64-bit words (reserved exponents among them, so NaN sums): the fused
+    kernel equals its verification variant and the GPU encode of its own single-precision sums,
+    and those codes follow the encode rule against the oracle (reserved code for NaN sums)"""
+    torch = torch_dev
+    say(f"case: axpy arbitrary codes {prec}")
+    c, co = vc.codec(precision=prec), O.codec()
+    n = (1 << 16) + 7
+    wa, wb = random_codes(n, 31), random_codes(n, 32)
+    ta, tb = up(torch, wa), up(torch, wb)
+    out = vc.vc_axpy(c, ALPHA, ta, tb)
+    out2, c32 = vc.vcx_axpy_dump(c, ALPHA, ta, tb)
+    torch.cuda.synchronize()
+    wc, wc2, c32 = down(out, True), down(out2, True), down(c32)
+    assert np.array_equal(wc, wc2)
+    assert np.array_equal(wc, gpu_encode(torch, c, c32))
+    res = classify(co, c32, wc)
+    nan_sums = int((~np.isfinite(c32).all(axis=1)).sum())
+    say(f"axpy arbitrary codes {prec}: {_summary(res)}, {nan_sums} non-finite sums")
+    assert nan_sums > 0 and res["other"] == 0, describe_bad(co, c32, wc, res)
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
