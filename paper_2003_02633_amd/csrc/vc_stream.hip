@@ -262,9 +262,10 @@ static vc_status axpy_launch(const Resolved& R, float alpha, const uint64_t* a, 
 {
   constexpr size_t TILE = (size_t)2 * BS * U;
   const bool aligned = (((uintptr_t)a | (uintptr_t)b | (uintptr_t)c) & 15u) == 0;
-  // tiles are counted in 32 bits (2^32 tiles of at least 256 codes exceed any HBM); past that
-  // count the kernel's one-vector-per-lane tail would take the rest
-  const size_t ntiles = aligned ? (n / TILE < 0xffffffffu ? n / TILE : 0xffffffffu) : 0;
+  // tiles are counted in 32 bits: at most 2^31 of them (2^40 codes and more, beyond any HBM), so
+  // that tile + grid (grid <= 2^30) cannot wrap; past that count the one-vector-per-lane tail
+  // would take the rest
+  const size_t ntiles = aligned ? (n / TILE < 0x80000000u ? n / TILE : 0x80000000u) : 0;
   const unsigned grid = grid_for(n, TILE, 1u << 30);
   if (dump)
     hipLaunchKernelGGL((k_axpy<L, MODE, PREC, BS, U, false, true>), dim3(grid), dim3(BS), 0, s, a, b, c, n,
