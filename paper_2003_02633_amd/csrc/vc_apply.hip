@@ -20,7 +20,7 @@
 //     written directly make 64 scattered 12-byte pieces per store; staged per 16-row block, each
 //     element's rows are contiguous and consecutive lanes store consecutive 8-byte pairs.
 // A workgroup is 8 waves (128 elements per step) sharing one copy of M, one workgroup per CU,
-// persistent over the element tiles.
+// persistent over the element tiles (the last, partial round spread over the CUs).
 #include "vc_internal.hpp"
 
 namespace vc {
@@ -58,8 +58,17 @@ __global__ __launch_bounds__(64 * APPLY_WAVES) void k_apply(const float* __restr
   const int wave = threadIdx.x >> 6;
   const int j = lane & 15;        // column within a tile = element within the wave's 16
   const int q = lane >> 4;        // K quarter
+  // Tiles: R full rounds in which wave w of workgroup b takes tile i W + 8 b + w (W waves in
+  // all), then the rem = ntiles mod W left over go one per wave in the order (w, b) = (0, 0),
+  // (0, 1), ...: waves 0-3 of every workgroup before any wave 4-7, so the last round spreads
+  // over as many CUs and SIMDs as it can instead of filling a few CUs with 8 waves each.
   const size_t ntiles = (n_elem + APPLY_EPW - 1) / APPLY_EPW;
-  for (size_t t = (size_t)blockIdx.x * APPLY_WAVES + wave; t < ntiles; t += (size_t)gridDim.x * APPLY_WAVES) {
+  const size_t W = (size_t)gridDim.x * APPLY_WAVES;
+  const size_t R = ntiles / W, rem = ntiles - R * W;
+  const size_t kx = (size_t)wave * gridDim.x + blockIdx.x;     // this wave's rank in the last round
+  const size_t mine = R + (kx < rem ? 1 : 0);
+  for (size_t i = 0; i < mine; i++) {
+    const size_t t = i < R ? i * W + (size_t)blockIdx.x * APPLY_WAVES + wave : R * W + kx;
     const size_t e = t * APPLY_EPW + j;
     const bool e_ok = e < n_elem;
     const uint64_t* Ue = U + (e_ok ? e : 0) * (size_t)cols;
