@@ -363,3 +363,10 @@ def test_dot_norm2(torch_dev, n):
     say(f"dot n={n}: gpu {d:.9e} oracle {ref_d:.9e}; norm2 gpu {s:.9e} oracle {ref_s:.9e}")
     assert abs(d - ref_d) <= 4e-6 * scale
     assert abs(s - ref_s) <= 4e-6 * ref_s
+    # operands one code in (8-byte but not 16-byte aligned: the one-code-per-load path)
+    if n > 1:
+        ta2, tb2 = up(torch, np.concatenate([wa[:1], wa])), up(torch, np.concatenate([wb[:1], wb]))
+        d2 = float(vc.vc_dot(c, ta2[1:], tb2[1:]).cpu()[0])
+        s2 = float(vc.vc_norm2(c, ta2[1:]).cpu()[0])
+        assert abs(d2 - ref_d) <= 4e-6 * scale
+        assert abs(s2 - ref_s) <= 4e-6 * ref_s
