@@ -42,8 +42,9 @@ vc_status vcb_axpy_f16x4(float alpha, const uint16_t* a, const uint16_t* b, uint
  * quantisation) for one encoder precision (VC_PREC_F64 or VC_PREC_F32; -1 sets both):
  * threads per block (128, 256, 512), vectors per thread and grid step (2, 4, or 8 with
  * 256 or 512 threads),
- * non-temporal loads/stores (0/1).  Process-wide; not thread-safe with concurrent
- * launches.  Unsupported combinations return VC_ERROR_UNSUPPORTED_CODEC and change nothing.
+ * non-temporal loads/stores (0/1).  Process-wide; a change may race with launches on other
+ * threads (each launch uses the configuration current when it is enqueued).  Unsupported
+ * combinations return VC_ERROR_UNSUPPORTED_CODEC and change nothing.
  * vcx_load_tuning reads lines "axpy f64 block=B vpt=V nt=T" (or f32, or no precision for
  * both) from a text file, the cache the autotuner writes; the library applies the file
  * named by $VC_TUNE_CACHE on the first vc_axpy call. */

@@ -1,5 +1,6 @@
 // vc_api.hip -- C ABI of libvc: argument validation, codec resolution, dispatch.
 #include <math.h>
+#include <mutex>
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -178,11 +179,11 @@ vc_status vcx_load_tuning(const char* path)
 
 static void apply_env_tuning()
 {
-  static bool done = false;
-  if (done) return;
-  done = true;
-  const char* p = getenv("VC_TUNE_CACHE");
-  if (p && *p) (void)vcx_load_tuning(p);
+  static std::once_flag once;                     // the first vc_axpy call of any thread
+  std::call_once(once, [] {
+    const char* p = getenv("VC_TUNE_CACHE");
+    if (p && *p) (void)vcx_load_tuning(p);
+  });
 }
 
 vc_status vc_axpy(const vc_codec* c, float alpha, const uint64_t* a, const uint64_t* b, uint64_t* out, size_t n,

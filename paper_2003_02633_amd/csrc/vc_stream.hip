@@ -7,6 +7,7 @@
 //   k_encode : float32 AoS -> codes                        -- compress(), §3
 //   k_decode : codes -> float32 AoS                        -- decompress(), Alg. (fr_fdiv_comp)
 //   k_dot / k_norm2 : FP32 reductions over decoded vectors
+#include <atomic>
 #include <type_traits>
 
 #include "vc_internal.hpp"
@@ -241,10 +242,20 @@ static inline unsigned grid_for(size_t work, size_t per_block, unsigned cap)
 }
 
 // ---- launch configuration of the streaming axpy per encoder precision (indexed by Prec), set by
-// the autotuner; defaults are the fastest configurations measured at N = 2^27 on MI355X
-static StreamCfg g_axpy_cfg[2] = {{512, 1, 1} /* PREC_F32 */, {512, 2, 1} /* PREC_F64 */};
+// the autotuner; defaults are the fastest configurations measured at N = 2^27 on MI355X.  Each is
+// one atomic word (block | vpt << 12 | nt << 20), so that a configuration change may race with
+// launches on other threads: a launch uses the configuration current when it reads it.
+static constexpr uint32_t pack_cfg(int block, int vpt, int nt)
+{
+  return (uint32_t)block | (uint32_t)vpt << 12 | (uint32_t)nt << 20;
+}
+static std::atomic<uint32_t> g_axpy_cfg[2] = {pack_cfg(512, 1, 1) /* PREC_F32 */, pack_cfg(512, 2, 1) /* PREC_F64 */};
 
-StreamCfg stream_cfg(int prec) { return g_axpy_cfg[prec == PREC_F64 ? 1 : 0]; }
+StreamCfg stream_cfg(int prec)
+{
+  const uint32_t v = g_axpy_cfg[prec == PREC_F64 ? 1 : 0].load(std::memory_order_relaxed);
+  return {(int)(v & 0xfffu), (int)((v >> 12) & 0xffu), (int)((v >> 20) & 1u)};
+}
 
 vc_status set_axpy_cfg(int prec, int block, int vpt, int nt)
 {
@@ -252,7 +263,7 @@ vc_status set_axpy_cfg(int prec, int block, int vpt, int nt)
   const bool oku = vpt == 1 || vpt == 2 || (vpt == 4 && block >= 256);   // grid steps of 2 codes per lane
   if (!okb || !oku || (nt != 0 && nt != 1) || prec < -1 || prec > 1) return VC_ERROR_UNSUPPORTED_CODEC;
   for (int p = 0; p < 2; p++)
-    if (prec < 0 || prec == p) g_axpy_cfg[p] = {block, vpt, nt};
+    if (prec < 0 || prec == p) g_axpy_cfg[p].store(pack_cfg(block, vpt, nt), std::memory_order_relaxed);
   return VC_SUCCESS;
 }
 
@@ -282,7 +293,7 @@ static vc_status axpy_t(const Resolved& R, float alpha, const uint64_t* a, const
 {
   // tuned variants for the default layout and uniform quantisation; other codecs use 512 x 2, NT
   if constexpr (std::is_same<L, L0722>::value && MODE == PLAIN) {
-    const StreamCfg g = g_axpy_cfg[PREC == PREC_F64 ? 1 : 0];
+    const StreamCfg g = stream_cfg(PREC);
     const int key = (g.block == 128 ? 0 : g.block == 256 ? 1 : 2) * 6 + (g.vpt == 4 ? 4 : g.vpt == 2 ? 2 : 0) + g.nt;
     switch (key) {
       case 0: return axpy_launch<L, MODE, PREC, 128, 1, false>(R, alpha, a, b, c, n, dump, s);

@@ -266,3 +266,34 @@ def test_vc_log_lines_without_device_work():
         assert lines[1].startswith("[vc] vc_axpy n=16 layout=0 mode=0 mag_round=0 precision=0 block=")
         assert lines[1].endswith("-> VC_ERROR_INVALID_VALUE")
         assert lines[2].startswith("[vc] vc_norm2 n=0 ") and lines[2].endswith("-> VC_ERROR_INVALID_VALUE")   # needs d_out
+
+
+def test_env_tuning_applied_once_under_concurrent_first_calls(tmp_path):
+    """$VC_TUNE_CACHE is applied exactly once, by whichever thread calls vc_axpy first, while
+    other threads change and read the configuration (validation-only calls, no GPU needed)"""
+    import subprocess
+    import sys
+    f = tmp_path / "tune.txt"
+    f.write_text("axpy f64 block=256 vpt=8 nt=0\n")
+    code = (
+        "import ctypes as C, threading, paper_2003_02633_amd as vc\n"
+        "L = vc.lib(); c = vc.codec(); seen = set(); errs = []\n"
+        "def axpy():\n"
+        "    for _ in range(200):\n"
+        "        if L.vc_axpy(C.byref(c), C.c_float(1.0), None, None, None, 0, None) != 0: errs.append('axpy')\n"
+        "def reader():\n"
+        "    for _ in range(200): seen.add(vc.get_stream_config('f64'))\n"
+        "ts = [threading.Thread(target=axpy) for _ in range(4)] + [threading.Thread(target=reader) for _ in range(4)]\n"
+        "[t.start() for t in ts]; [t.join() for t in ts]\n"
+        "assert not errs, errs\n"
+        "assert vc.get_stream_config('f64') == (256, 8, 0), vc.get_stream_config('f64')\n"
+        "assert seen <= {(512, 4, 1), (256, 8, 0)}, seen\n"
+        "vc.set_stream_config(512, 4, 1, 'f64')\n"
+        "L.vc_axpy(C.byref(c), C.c_float(1.0), None, None, None, 0, None)\n"
+        "assert vc.get_stream_config('f64') == (512, 4, 1)   # not re-applied\n"
+        "print('ok')\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, VC_TUNE_CACHE=str(f))
+    env.pop("VC_LOG", None)
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, env=env, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0 and r.stdout.strip().endswith("ok"), r.stderr[-2000:]
