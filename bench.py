@@ -96,6 +96,21 @@ def read_valu(n: int):
         return None
 
 
+# VALU issue ceiling of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-instructions per second
+# (a wave64 instruction occupies a SIMD16 for 4 cycles; packed FP32 is compiled out)
+VALU_PEAK_LANE_INSTR_PER_S = 256 * 4 * 16 * 2.4e9
+
+
+def valu_view(v, n: int, ms: float):
+    """The ALU side of the roofline: the profiled VALU instructions per vector times the vectors
+    per second of this run, against the issue ceiling (busy fraction from the same profile)."""
+    if not v:
+        return None
+    rate = v["valu_instr_per_vector"] * n / (ms * 1e-3)
+    return dict(v, achieved_lane_instr_per_s=rate, peak_lane_instr_per_s=VALU_PEAK_LANE_INSTR_PER_S,
+                issue_frac=rate / VALU_PEAK_LANE_INSTR_PER_S)
+
+
 # Side-by-side timings warm up by time, not count: the clocks drop within milliseconds of idle
 # (host-side set-up between measurements) and take tens of milliseconds of load to come back up.
 WX = None
@@ -546,7 +561,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": read_traffic(N),
                      "algorithmic_bytes_per_launch": 24 * N, "copy_GBs": extras.get("copy", {}).get("GBs"),
-                     "valu": read_valu(N)},
+                     "valu": valu_view(read_valu(N), N, ms)},
         "cpu_baseline": cpu,
         "extras": extras,
     }
