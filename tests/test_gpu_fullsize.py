@@ -2,7 +2,8 @@
 outputs the oracle computes one by one (and properties that hold at any size).
 
   axpy     N = 2^27, directions uniform on S^2, |x| = 10^U[-6, 6], alpha = RN32(0.7), the tuned
-           launch of vc_axpy, for the plain codec (both encoders) and the variants
+           launch of vc_axpy, for the plain codec (both encoders), the variants and the
+           truncating magnitude
   apply    200,000 p = 4 elements of the Taylor-Green field, operator 150 x 125
   batch    64 segments of floor(10^U[3, 7]) vectors, axpy / dot / norm2 / encode
   errhist  2^25 von Mises-Fisher vectors (kappa 1000 about +z), against the oracle's histogram
@@ -58,7 +59,8 @@ def _u64(t):
 
 @pytest.mark.parametrize("label,kw", [("plain-f64", {"precision": "f64"}), ("plain-f32", {"precision": "f32"}),
                                       ("frac163840", {"mode": "frac", "P": 163840}),
-                                      ("tanh0.5", {"mode": "tanh", "gamma": 0.5}), ("cos", {"mode": "cos"})])
+                                      ("tanh0.5", {"mode": "tanh", "gamma": 0.5}), ("cos", {"mode": "cos"}),
+                                      ("trunc", {"mag_round": "trunc"})])
 def test_axpy_full_size(torch_dev, operands, label, kw):
     torch = torch_dev
     say(f"case: full-size axpy {label} N=2^27")
@@ -94,8 +96,10 @@ def test_axpy_full_size(torch_dev, operands, label, kw):
     elif kw.get("mode") == "cos":
         stretch = None
     err = np.linalg.norm(got - c64, axis=1)[ok]
+    # magnitude: nearest-even at 23 bits, or (truncation) nearest-even at 24 then one bit dropped
+    mag = 2.0 ** -22 + 2.0 ** -24 if kw.get("mag_round") == "trunc" else 2.0 ** -23
     if stretch is not None:
-        bound = (math.hypot(math.pi / nt, math.pi / (2 * npm)) / stretch + 2.0 ** -23) * nrm[ok] \
+        bound = (math.hypot(math.pi / nt, math.pi / (2 * npm)) / stretch + mag) * nrm[ok] \
             + (4 * 2.0 ** -24 + 1e-6) * scale[ok]
         say(f"{label}: max end-to-end err/allowed {(err / bound).max():.3f}")
         assert (err <= bound).all()
