@@ -47,7 +47,10 @@ def _check(co, M, U, got, label):
 
 
 @pytest.mark.parametrize("rows,cols,n_elem", [(150, 125, 1000), (150, 125, 17), (1, 1, 5), (16, 4, 33),
-                                              (32, 8, 64), (47, 125, 100), (256, 20, 40), (150, 125, 1)])
+                                              (32, 8, 64), (47, 125, 100), (256, 20, 40), (150, 125, 1),
+                                              # 2,054 tiles on 256 workgroups of 8 waves: one full round
+                                              # and 6 tiles spread over the workgroups' first waves
+                                              (16, 4, 16 * 2054 - 13)])
 def test_apply_shapes(torch_dev, rows, cols, n_elem):
     say(f"case: apply rows={rows} cols={cols} n_elem={n_elem}")
     c, co = vc.codec(), O.codec()
