@@ -5,7 +5,9 @@ Workload (one "step" = one pass of the whole hot path = one launch of the fused
 decode-FMA-encode kernel): c = alpha*a + b on N = 2^27 compressed 3-vectors
 (<0,7,22>-17-18 codes, 1 GiB per operand), directions uniform on S^2, magnitudes
 log-uniform on [1e-6, 1e6], alpha = 0.7.  Inputs are generated and encoded on the
-GPU before timing, so they are resident in HBM.
+GPU before timing, so they are resident in HBM.  Before the W warm-up steps the same
+launch runs untimed for 200 ms of wall time (the GPU clocks take tens of milliseconds of
+load to ramp); then exactly K steps are timed with HIP events.
 
 Prints one JSON line: metric/value (Gvec/s of the compressed axpy), the HBM
 roofline of that kernel, the CPU oracle timed on the host on a bounded sample, and
@@ -32,8 +34,8 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E spec
 ALPHA = 0.699999988079071      # float32(0.7)
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "axpy_n2p27_traffic.txt")
 PROFILE_VALU = os.path.join(ROOT, "profiles", "axpy_n2p27_valu.txt")
-KERNEL_SOURCES = ["paper_2003_02633_amd/csrc/vc_device.hpp", "paper_2003_02633_amd/csrc/vc_stream.hip",
-                  "paper_2003_02633_amd/csrc/vc_coeffs.inc"]
+KERNEL_SOURCES = ["include/vc_device.hpp", "paper_2003_02633_amd/csrc/vc_stream.hip",
+                  "include/vc_coeffs.inc"]
 
 
 def log(msg):
@@ -114,7 +116,21 @@ def valu_view(v, n: int, ms: float):
 # Side-by-side timings warm up by time, not count: the clocks drop within milliseconds of idle
 # (host-side set-up between measurements) and take tens of milliseconds of load to come back up.
 WX = None
-SETTLE_MS = 100.0
+SETTLE_MS = 200.0
+
+
+def settle(torch, fn, ms: float = None):
+    """back-to-back untimed calls of fn(), checked every 8, until `ms` (SETTLE_MS) of wall time
+    has passed: brings the GPU clocks up before anything is timed"""
+    import time
+
+    limit = SETTLE_MS if ms is None else ms
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while (time.perf_counter() - t0) * 1e3 < limit:
+        for _ in range(8):
+            fn()
+        torch.cuda.synchronize()
 
 
 def timed(torch, fn, steps: int, warmup) -> float:
@@ -123,13 +139,7 @@ def timed(torch, fn, steps: int, warmup) -> float:
     import time
 
     if warmup is None:
-        # back-to-back calls, checked every 8, until SETTLE_MS of wall time has passed
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        while (time.perf_counter() - t0) * 1e3 < SETTLE_MS:
-            for _ in range(8):
-                fn()
-            torch.cuda.synchronize()
+        settle(torch, fn)
     else:
         for _ in range(warmup):
             fn()
@@ -429,8 +439,12 @@ def main():
                           "kernel_hash": kernel_hash()}), flush=True)
         return
 
-    log(f"timing compressed axpy: warmup {args.warmup}, steps {args.steps}")
-    ms = timed(torch, lambda: vc.vc_axpy(c, ALPHA, wa, wb, wc), args.steps, args.warmup)
+    log(f"timing compressed axpy: clock settle {SETTLE_MS:.0f} ms, warmup {args.warmup}, steps {args.steps}")
+    step = lambda: vc.vc_axpy(c, ALPHA, wa, wb, wc)
+    # the clocks ramp over tens of milliseconds of load: untimed launches for SETTLE_MS of wall
+    # time first, then the W warm-up launches, then exactly the K timed ones
+    settle(torch, step)
+    ms = timed(torch, step, args.steps, args.warmup)
     gvecs = N / (ms * 1e-3) / 1e9
     achieved = 24.0 * N / (ms * 1e-3) / 1e9
     log(f"compressed axpy: {ms:.3f} ms/step, {gvecs:.2f} Gvec/s, {achieved:.0f} GB/s")

@@ -78,12 +78,14 @@ VC_DI float asin_(float x) { return asinf(x); }
 #endif
 #ifdef VC_HOST_EMULATION
 VC_DI uint64_t dbits(double d) { uint64_t u; memcpy(&u, &d, 8); return u; }
+VC_DI double dfrom_bits(uint64_t u) { double d; memcpy(&d, &u, 8); return d; }
 VC_DI double rsq64_(double x) { return (1.0 / sqrt(x)) * (1.0 + 3e-8); }   // crude, like v_rsq_f64
 VC_DI double rcp64_(double x) { return (1.0 / x) * (1.0 - 4e-8); }
 VC_DI double floor64_(double x) { return floor(x); }
 VC_DI double fma64_(double a, double b, double c) { return fma(a, b, c); }
 #else
 VC_DI uint64_t dbits(double d) { return (uint64_t)__double_as_longlong(d); }
+VC_DI double dfrom_bits(uint64_t u) { return __longlong_as_double((long long)u); }
 VC_DI double rsq64_(double x) { return __builtin_amdgcn_rsq(x); }   // v_rsq_f64, ~2^-24
 VC_DI double rcp64_(double x) { return __builtin_amdgcn_rcp(x); }   // v_rcp_f64, ~2^-24
 VC_DI double floor64_(double x) { return __builtin_floor(x); }
@@ -171,6 +173,7 @@ struct Params {
   double Kt64, Np64;         // n_theta_max/2, n_phi_max
   double Ct64, Cp64;         // (n_theta_max/2)/pi, n_phi_max/pi
   double invKt64, invKc64;   // 1/(n_theta_max/2), 1/(n_phi_max/2)
+  double invT64;             // fractional split: RN64(1/T) (decode quotient)
   double w64[16];            // tanh: h(u)/u = sum w64[i] (u^2)^i
 };
 
@@ -206,17 +209,32 @@ VC_DI void decode_fields(uint64_t w, const Params& P, float& r, uint32_t& nth, u
   if (MODE == FRAC) {
     const uint64_t np = w & ((1ull << (L::p + L::t)) - 1ull);
     if (np >= P.limit) r = ubits(0x7fc00000u);
-    // np / T by a float estimate and an exact integer correction
-    uint32_t q = (uint32_t)((float)np * rcp_((float)P.T));
-    int64_t rem = (int64_t)np - (int64_t)q * (int64_t)P.T;
-    if (rem < 0) { q -= 1; rem += P.T; }
-    if (rem >= (int64_t)P.T) { q += 1; rem -= P.T; }
-    nph = q;
-    nth = (uint32_t)rem;
+    // n_phi = floor(np / T), n_theta = np mod T.  np < 2^35 is exact in a double (its bits placed
+    // in the mantissa of 2^52); with invT64 = RN64(1/T) the product is within 2^-27 of np / T
+    // (np / T < 2^24), while np / T lies at least 1/T >= 2^-24 from the next integer above, so
+    // the truncated estimate is the quotient or, when T divides np, one less: one upward
+    // correction of the 32-bit remainder (< 2 T <= 2^25) finishes it.  The clamp keeps the
+    // conversion in range for codes past the limit (their magnitude is NaN).
+    const double npd = dfrom_bits(0x4330000000000000ull | np) - 0x1p52;
+    const uint32_t q0 = (uint32_t)fmin64_nn(npd * P.invT64, 0x1p25);
+    const uint32_t rem = (uint32_t)np - q0 * P.T;
+    const bool up = rem >= P.T;
+    nph = up ? q0 + 1u : q0;
+    nth = up ? rem - P.T : rem;
   } else {
     nth = (uint32_t)w & ((1u << L::t) - 1u);
     nph = (uint32_t)(w >> L::sh_p) & ((1u << L::p) - 1u);
   }
+}
+
+// Magnitude of a code as a norm sees it: r_hat (decode_mag), and NaN for fractional-split codes
+// past the limit P T, which decode to NaN (Eq. q_split has no level pair for them).
+template <class L, int MODE>
+VC_DI float decode_mag_checked(uint64_t w, const Params& P)
+{
+  float r = decode_mag<L>(w);
+  if (MODE == FRAC && (w & ((1ull << (L::p + L::t)) - 1ull)) >= P.limit) r = ubits(0x7fc00000u);
+  return r;
 }
 
 // A level count times 1/n_max (or 1/(2 n_max)).  For the uniform levels of every layout

@@ -26,7 +26,7 @@
 
 #include <stdint.h>
 
-#include "../paper_2003_02633_amd/csrc/vc_device.hpp"
+#include "vc_device.hpp"
 
 namespace vc_inline {
 

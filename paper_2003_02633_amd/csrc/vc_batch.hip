@@ -133,7 +133,7 @@ __global__ __launch_bounds__(BB) void k_batch(const BatchSeg* __restrict__ segs,
         if (dot) {
           acc += dot_pair<L, MODE>(wa[h], wb[h], P);
         } else {
-          const float r = decode_mag<L>(wa[h]);
+          const float r = decode_mag_checked<L, MODE>(wa[h], P);
           acc = __builtin_fmaf(r, r, acc);
         }
       }

@@ -6,7 +6,7 @@
 #include <stdint.h>
 
 #include "../../include/vc.h"
-#include "vc_device.hpp"
+#include "../../include/vc_device.hpp"
 #include "vc_params.hpp"
 
 namespace vc {

@@ -7,7 +7,7 @@
 #include <string.h>
 
 #include "../../include/vc.h"
-#include "vc_device.hpp"
+#include "../../include/vc_device.hpp"
 
 namespace vc {
 
@@ -191,6 +191,7 @@ inline vc_status resolve(const vc_codec* c, Resolved* R)
     np = c->frac_P - 1;
     P.T = (uint32_t)T;
     P.limit = c->frac_P * T;
+    P.invT64 = 1.0 / (double)T;
   } else {
     nt = (1ull << lb.t) - 1;
     np = (1ull << lb.p) - 1;

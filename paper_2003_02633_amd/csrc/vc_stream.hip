@@ -210,12 +210,13 @@ __global__ __launch_bounds__(BS) void k_dot(const uint64_t* __restrict__ a, cons
   if (threadIdx.x == 0) parts[blockIdx.x] = s;
 }
 
-template <class L, int BS>
-__global__ __launch_bounds__(BS) void k_norm2(const uint64_t* __restrict__ a, size_t n, float* __restrict__ parts)
+template <class L, int MODE, int BS>
+__global__ __launch_bounds__(BS) void k_norm2(const uint64_t* __restrict__ a, size_t n, Params P,
+                                              float* __restrict__ parts)
 {
   float acc = 0.0f;
   for (size_t i = (size_t)blockIdx.x * BS + threadIdx.x; i < n; i += (size_t)gridDim.x * BS) {
-    const float r = decode_mag<L>(a[i]);
+    const float r = decode_mag_checked<L, MODE>(a[i], P);
     acc = __builtin_fmaf(r, r, acc);
   }
   const float s = block_sum<BS>(acc);
@@ -367,10 +368,11 @@ static vc_status dot_t(const Resolved& R, const uint64_t* a, const uint64_t* b, 
   return launch_status();
 }
 
-template <class L>
-static vc_status norm2_t(const uint64_t* a, size_t n, float* parts, int np, float* out, hipStream_t s)
+template <class L, int MODE, int PREC>
+static vc_status norm2_t(const Resolved& R, const uint64_t* a, size_t n, float* parts, int np, float* out,
+                         hipStream_t s)
 {
-  hipLaunchKernelGGL((k_norm2<L, 256>), dim3(np), dim3(256), 0, s, a, n, parts);
+  hipLaunchKernelGGL((k_norm2<L, MODE, 256>), dim3(np), dim3(256), 0, s, a, n, R.P, parts);
   vc_status st = launch_status();
   if (st != VC_SUCCESS) return st;
   hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(256), 0, s, (const float*)parts, np, out);
@@ -402,13 +404,7 @@ vc_status launch_dot(const Resolved& R, const uint64_t* a, const uint64_t* b, si
 vc_status launch_norm2(const Resolved& R, const uint64_t* a, size_t n, float* parts, int np, float* out,
                        hipStream_t s)
 {
-  switch (R.layout) {
-    case 0: return norm2_t<L0722>(a, n, parts, np, out, s);
-    case 1: return norm2_t<L0723>(a, n, parts, np, out, s);
-    case 2: return norm2_t<L0823>(a, n, parts, np, out, s);
-    case 3: return norm2_t<L1823>(a, n, parts, np, out, s);
-    default: return VC_ERROR_UNSUPPORTED_CODEC;
-  }
+  VC_DISPATCH_NOPREC(R, norm2_t, R, a, n, parts, np, out, s);
 }
 
 }  // namespace vc

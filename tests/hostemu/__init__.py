@@ -14,8 +14,9 @@ _lib = None
 
 def build():
     os.makedirs(OUT_DIR, exist_ok=True)
-    deps = [SRC] + [os.path.join(HERE, "..", "..", "paper_2003_02633_amd", "csrc", f)
-                    for f in ("vc_device.hpp", "vc_params.hpp", "vc_coeffs.inc")]
+    root = os.path.join(HERE, "..", "..")
+    deps = [SRC, os.path.join(root, "paper_2003_02633_amd", "csrc", "vc_params.hpp")] + \
+        [os.path.join(root, "include", f) for f in ("vc_device.hpp", "vc_coeffs.inc", "vc.h")]
     if os.path.exists(LIB) and all(os.path.getmtime(LIB) >= os.path.getmtime(d) for d in deps):
         return LIB
     # a private temporary per process, then an atomic rename: parallel test workers may build at
@@ -36,6 +37,7 @@ def lib():
         L.emu_encode.argtypes = [vp, vp, vp, C.c_size_t]
         L.emu_decode.argtypes = [vp, vp, vp, C.c_size_t]
         L.emu_dot_pair.argtypes = [vp, vp, vp, vp, C.c_size_t]
+        L.emu_magnitude_checked.argtypes = [vp, vp, vp, C.c_size_t]
         L.emu_exact_norm.argtypes = [C.c_float, C.c_float, C.c_float, C.c_int, C.c_int,
                                      C.POINTER(C.c_uint32), C.POINTER(C.c_int)]
         _lib = L
@@ -57,6 +59,16 @@ def decode(codec, w):
     st = lib().emu_decode(C.addressof(codec), w.ctypes.data, out.ctypes.data, w.shape[0])
     if st:
         raise RuntimeError(f"emu_decode status {st}")
+    return out
+
+
+def magnitude_checked(codec, w):
+    """per-code magnitude as the norm kernels take it (NaN past a fractional split's P T levels)"""
+    w = np.ascontiguousarray(np.asarray(w).astype(np.uint64).reshape(-1))
+    out = np.empty(w.shape[0], dtype=np.float32)
+    st = lib().emu_magnitude_checked(C.addressof(codec), w.ctypes.data, out.ctypes.data, w.shape[0])
+    if st:
+        raise RuntimeError(f"emu_magnitude_checked status {st}")
     return out
 
 

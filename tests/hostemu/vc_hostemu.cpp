@@ -1,6 +1,6 @@
 // CPU emulation build of the device codec (test infrastructure).
 //
-// Compiles paper_2003_02633_amd/csrc/vc_device.hpp for the host with libm
+// Compiles include/vc_device.hpp for the host with libm
 // stand-ins for the AMDGPU builtins (v_sin/v_cos/v_rsq/v_rcp are replaced by
 // FP64-based equivalents), so the codec's integer logic, octant reduction,
 // double-float level arithmetic and exact magnitude path can be checked against
@@ -22,6 +22,12 @@ template <class L, int MODE>
 static void dec(const Params& P, const uint64_t* w, float* out, size_t n)
 {
   for (size_t i = 0; i < n; i++) decode_vec<L, MODE>(w[i], P, out[3 * i], out[3 * i + 1], out[3 * i + 2]);
+}
+
+template <class L, int MODE>
+static void magc(const Params& P, const uint64_t* w, float* out, size_t n)
+{
+  for (size_t i = 0; i < n; i++) out[i] = decode_mag_checked<L, MODE>(w[i], P);
 }
 
 template <class L, int MODE>
@@ -63,6 +69,15 @@ int emu_decode(const vc_codec* c, const uint64_t* w, float* out, size_t n)
   vc_status st = resolve(c, &R);
   if (st != VC_SUCCESS) return st;
   EMU_DISPATCH(R, dec, R.P, w, out, n);
+  return 0;
+}
+
+int emu_magnitude_checked(const vc_codec* c, const uint64_t* w, float* out, size_t n)
+{
+  Resolved R;
+  vc_status st = resolve(c, &R);
+  if (st != VC_SUCCESS) return st;
+  EMU_DISPATCH(R, magc, R.P, w, out, n);
   return 0;
 }
 

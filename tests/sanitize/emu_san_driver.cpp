@@ -17,6 +17,7 @@ int emu_encode(const vc_codec* c, const float* xyz, uint64_t* out, size_t n);
 int emu_decode(const vc_codec* c, const uint64_t* w, float* out, size_t n);
 int emu_dot_pair(const vc_codec* c, const uint64_t* a, const uint64_t* b, float* out, size_t n);
 int emu_exact_norm(float x, float y, float z, int prec, int keep_sub, uint32_t* j, int* g);
+int emu_magnitude_checked(const vc_codec* c, const uint64_t* w, float* out, size_t n);
 }
 
 static uint64_t state = 0x2545f4914f6cdd1dull;
@@ -69,12 +70,17 @@ int main()
           c.layout = layout; c.mode = mode; c.mag_round = mag; c.precision = prec;
           c.compand_mask = VC_COMPAND_PHI | VC_COMPAND_THETA;
           c.gamma = 0.5f;
-          c.frac_P = 163840;
-          if (emu_encode(&c, xyz.data(), w.data(), n) != 0) continue;   // combination not built
-          if (emu_decode(&c, w.data(), out.data(), n) != 0) return 2;
-          if (emu_decode(&c, r.data(), out.data(), n) != 0) return 2;
-          if (emu_dot_pair(&c, w.data(), r.data(), d.data(), n) != 0) return 2;
-          runs++;
+          // the fractional split at a moderate and at the largest accepted level count
+          for (uint64_t P : {163840ull, 1ull << 24}) {
+            c.frac_P = P;
+            if (emu_encode(&c, xyz.data(), w.data(), n) != 0) break;   // combination not built
+            if (emu_decode(&c, w.data(), out.data(), n) != 0) return 2;
+            if (emu_decode(&c, r.data(), out.data(), n) != 0) return 2;
+            if (emu_dot_pair(&c, w.data(), r.data(), d.data(), n) != 0) return 2;
+            if (emu_magnitude_checked(&c, r.data(), d.data(), n) != 0) return 2;
+            runs++;
+            if (mode != VC_MODE_FRACSPLIT) break;
+          }
         }
   for (size_t k = 0; k < n; k++) {
     const float x = xyz[3 * k], y = xyz[3 * k + 1], z = xyz[3 * k + 2];

@@ -203,3 +203,43 @@ def test_emulated_exact_norm_path():
             S = exact_sq_norm(x, y, z)
             ref = round_sqrt(S, prec, Fraction(1, 1 << 149) if keep else None)
             assert Fraction(j) * Fraction(2) ** gexp == ref, (x, y, z, prec, keep)
+
+
+def _frac_quotient_codes(P, T, n, seed):
+    """codes of the <0,7,22> layout whose low 35-bit field n_p covers the valid range [0, P T):
+    uniform draws, exact multiples of T (remainder zero, where an estimate of n_p / T from below
+    truncates one short), their neighbours, and the ends of the range"""
+    g = np.random.default_rng(seed)
+    lim = P * T
+    k = g.integers(1, P, n // 4, dtype=np.uint64)
+    npf = np.concatenate([g.integers(0, lim, n // 4, dtype=np.uint64), k * np.uint64(T),
+                          k * np.uint64(T) - np.uint64(1), k * np.uint64(T) + np.uint64(1),
+                          np.array([0, 1, T - 1, T, lim - T, lim - 1, lim, lim + 1], dtype=np.uint64)])
+    E = g.integers(1, 127, npf.size, dtype=np.uint64)
+    M = g.integers(0, 1 << 22, npf.size, dtype=np.uint64)
+    return (E << np.uint64(57)) | (M << np.uint64(35)) | npf
+
+
+@pytest.mark.parametrize("P", [163840, 1 << 20, 1 << 22, 12_000_000, 16_000_001, (1 << 24) - 3, 1 << 24])
+def test_emulated_frac_decode_large_P(P):
+    """Fractional split (§2.4, Eq. q_split) with up to 2^24 phi levels: n_phi = floor(n_p / T) and
+    n_theta = n_p mod T decode as the oracle's integer division does, including n_p at multiples
+    of T, for every n_phi_max + 1 the library accepts (P <= 2^24)"""
+    c, co = _pair("0,7,22-17-18", "frac", {"P": P})
+    T = O.frac_T(co)
+    w = _frac_quotient_codes(P, T, 200_000, P % 1000)
+    assert decode_abs_err(co, w, H.decode(c, w)) <= 0.0
+    # the round trip through the encoder stays on valid fields
+    assert decode_abs_err(co, w[:20000], H.decode(c, w[:20000])) <= 0.0
+
+
+def test_emulated_norm2_magnitude_frac_limit():
+    """norm2's magnitude of a fractional-split code is NaN past the P T levels, as its decode is"""
+    c, co = _pair("0,7,22-17-18", "frac", {"P": 163840})
+    T = O.frac_T(co)
+    w = _frac_quotient_codes(163840, T, 4000, 3)
+    ref = O.decode64(co, w)
+    mag = H.magnitude_checked(c, w)
+    assert np.array_equal(np.isnan(mag), np.isnan(ref).any(axis=1))
+    fin = ~np.isnan(mag)
+    assert np.allclose(mag[fin].astype(np.float64), np.linalg.norm(ref[fin], axis=1), rtol=1e-6, atol=0)

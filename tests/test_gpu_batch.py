@@ -1,14 +1,19 @@
 """GPU parity of the batched persistent launch (vc_batch_plan_*) over a segment table.
 
 Contract:
-  * axpy / encode segments: codes bit-identical to the single-call entry points (vc_axpy,
-    vc_encode) on the same operands -- the persistent kernel runs the same per-vector codec;
-    those entry points are held to the oracle by test_gpu_parity;
+  * axpy segments: against the oracle, in the layered form of the single-call axpy: the codes
+    follow the encode rule (bit-exact up to counted one-level differences inside the one-ulp
+    window) on the single-precision sums alpha decode(a) + decode(b) of the same operands, and
+    decoding them recovers the FP64 sum of the oracle's exact decodes within the codec bound;
+  * encode segments: the encode rule against the oracle on the segment's own input;
+  * both: also bit-identical to the single-call entry points (vc_axpy, vc_encode) on the same
+    operands -- the persistent kernel runs the same per-vector codec;
   * dot / norm2 segments: within 4e-6 of sum |a||b| (resp. sum |a|^2) of the FP64 oracle;
     deterministic (two replays agree bit for bit); an empty segment gives exactly 0;
   * graph replays: every replay, with eager work in between, rewrites the same results;
   * the separate-launch paths (plain and graph-captured) agree with each other bit for bit.
 """
+import math
 import sys
 
 import numpy as np
@@ -17,6 +22,7 @@ import pytest
 import oracle as O
 import paper_2003_02633_amd as vc
 from paper_2003_02633_amd import inputs
+from tests.parity import classify, describe_bad
 
 pytestmark = pytest.mark.gpu
 
@@ -78,20 +84,50 @@ def build_segments(torch, co, lengths, ops, pad_every=0):
 
 
 def expected_codes(torch, c, segs):
-    """per axpy/encode segment: the single-call entry point's result"""
-    exp = {}
+    """per axpy/encode segment: the single-call entry point's result, and for axpy segments the
+    single-precision sums alpha decode(a) + decode(b) of the same operands (the verification
+    variant of the axpy kernel writes them)"""
+    exp, sums = {}, {}
     for i, s in enumerate(segs):
         if s["n"] == 0:
             continue
         if s["op"] == "axpy":
             exp[i] = vc.vc_axpy(c, ALPHA, s["a"], s["b"]).cpu()
+            _, c32 = vc.vcx_axpy_dump(c, ALPHA, s["a"], s["b"])
+            sums[i] = c32.cpu().numpy()
         elif s["op"] == "encode":
             exp[i] = vc.vc_encode(c, s["a"].view(-1, 3)).cpu()
     torch.cuda.synchronize()
+    exp["sums"] = sums
     return exp
 
 
-def check_results(torch, co, segs, host, exp, label):
+def check_codes_against_oracle(co, s, h, got, c32, label):
+    """the oracle side of an axpy / encode segment's codes"""
+    codes = got.numpy().view(np.uint64)
+    if s["op"] == "encode":
+        res = classify(co, h["x"], codes)
+        assert res["other"] == 0, f"{label}: encode segment\n" + describe_bad(co, h["x"], codes, res)
+        return
+    res = classify(co, c32, codes)
+    assert res["other"] == 0, f"{label}: axpy segment\n" + describe_bad(co, c32, codes, res)
+    A64, B64 = O.decode64(co, h["wa"]), O.decode64(co, h["wb"])
+    c64 = ALPHA * A64 + B64
+    dec = O.decode64(co, codes)
+    nrm = np.linalg.norm(c64, axis=1)
+    scale = ALPHA * np.linalg.norm(A64, axis=1) + np.linalg.norm(B64, axis=1)
+    ok = (nrm > 2.0 ** -70) & (nrm < 1e14)
+    nt, npm = O.nmax(co)
+    bound = (math.hypot(math.pi / nt, math.pi / (2 * npm)) + MAG_ERR[co.mag_round]) * nrm[ok] \
+        + (4 * 2.0 ** -24 + 1e-6) * scale[ok]
+    assert (np.linalg.norm(dec - c64, axis=1)[ok] <= bound).all(), f"{label}: axpy end-to-end bound"
+
+
+# magnitude error of nearest-even at 23 bits, and of the paper's truncation (24 bits, one dropped)
+MAG_ERR = {O.RNE: 2.0 ** -23, O.TRUNC: 2.0 ** -22 + 2.0 ** -24}
+
+
+def check_results(torch, co, segs, host, exp, label, oracle_codes=True):
     torch.cuda.synchronize()
     red = {}
     for i, s in enumerate(segs):
@@ -101,6 +137,8 @@ def check_results(torch, co, segs, host, exp, label):
                 continue
             got = s["out"][:n].cpu()
             assert torch.equal(got, exp[i]), f"{label}: segment {i} ({s['op']}, n={n}) differs"
+            if oracle_codes:
+                check_codes_against_oracle(co, s, host[i], got, exp["sums"].get(i), f"{label} segment {i}")
         else:
             v = float(s["out"].cpu()[0])
             red[i] = v
@@ -152,16 +190,16 @@ def test_batch_mixed_segments(torch_dev, precision):
         torch.cuda.synchronize()
         del scratch
         plan.run()
-        again = check_results(torch, co, segs, host, exp, f"replay {rep}")
+        again = check_results(torch, co, segs, host, exp, f"replay {rep}", oracle_codes=False)
         assert again == first, "reductions not deterministic across replays"
 
     clobber(torch, segs)
     plan.run_separate()
-    sep = check_results(torch, co, segs, host, exp, "separate")
+    sep = check_results(torch, co, segs, host, exp, "separate", oracle_codes=False)
     for rep in range(2):
         clobber(torch, segs)
         plan.run_separate_graph()
-        sep_g = check_results(torch, co, segs, host, exp, f"separate graph {rep}")
+        sep_g = check_results(torch, co, segs, host, exp, f"separate graph {rep}", oracle_codes=False)
         assert sep_g == sep
     plan.close()
 

@@ -370,3 +370,67 @@ def test_dot_norm2(torch_dev, n):
         s2 = float(vc.vc_norm2(c, ta2[1:]).cpu()[0])
         assert abs(d2 - ref_d) <= 4e-6 * scale
         assert abs(s2 - ref_s) <= 4e-6 * ref_s
+
+
+# ----------------------------------------------------------------------------- fractional split
+def _frac_codes(P, T, n, seed):
+    """<0,7,22> codes whose 35-bit field n_p covers [0, P T] and a little past it: uniform draws,
+    exact multiples of T and their neighbours, the range ends"""
+    g = np.random.default_rng(seed)
+    lim = P * T
+    k = g.integers(1, P, n // 4, dtype=np.uint64)
+    npf = np.concatenate([g.integers(0, lim + (lim >> 6), n // 4, dtype=np.uint64), k * np.uint64(T),
+                          k * np.uint64(T) - np.uint64(1), k * np.uint64(T) + np.uint64(1),
+                          np.array([0, 1, T - 1, T, lim - T, lim - 1, lim, lim + 1], dtype=np.uint64)])
+    E = g.integers(1, 127, npf.size, dtype=np.uint64)
+    M = g.integers(0, 1 << 22, npf.size, dtype=np.uint64)
+    return (E << np.uint64(57)) | (M << np.uint64(35)) | npf
+
+
+@pytest.mark.parametrize("P", [163840, 12_000_000, (1 << 24) - 3, 1 << 24])
+def test_frac_decode_large_P(torch_dev, P):
+    """Eq. (q_split) with up to 2^24 phi levels: the decode's quotient n_p / T and remainder
+    match the oracle's integer division for every accepted P (decoded values within 1e-6 r_hat,
+    NaN exactly past P T); encoding round-trips on the same codec follow the encode rule"""
+    say(f"case: frac decode P={P}")
+    c, co = vc.codec(mode="frac", P=P), O.codec(mode="frac", P=P)
+    T = O.frac_T(co)
+    w = _frac_codes(P, T, 1 << 18, P % 997)
+    d = down(vc.vc_decode(c, up(torch_dev, w)))
+    assert decode_abs_err(co, w, d) <= 0.0
+    x = inputs.sphere_loguniform(1 << 16, 3)
+    dev = gpu_encode(torch_dev, c, x)
+    res = classify(co, x, dev)
+    assert res["other"] == 0, describe_bad(co, x, dev, res)
+
+
+@pytest.mark.parametrize("mode,kw", [("plain", {}), ("frac", {"P": 163840}), ("frac", {"P": 1 << 24})])
+def test_norm2_dot_of_codes_against_oracle(torch_dev, mode, kw):
+    """norm2 = sum |decode(w)|^2 and dot over valid codes of every field value, and NaN where
+    some code decodes to NaN (fractional-split fields past P T), as in the oracle"""
+    torch = torch_dev
+    say(f"case: norm2/dot codes {mode} {kw}")
+    c, co = vc.codec(mode=mode, **kw), O.codec(mode=mode, **kw)
+    if mode == "frac":
+        T = O.frac_T(co)
+        w = _frac_codes(kw["P"], T, 1 << 16, 5)
+        valid = (w & np.uint64((1 << 35) - 1)) < np.uint64(kw["P"] * T)
+    else:
+        g = np.random.default_rng(6)
+        n = 1 << 16
+        w = (g.integers(1, 127, n, dtype=np.uint64) << np.uint64(57)) | \
+            (g.integers(0, 1 << 57, n, dtype=np.uint64))
+        valid = np.ones(n, dtype=bool)
+    wv = w[valid]
+    wb = np.roll(wv, 1)
+    for codes, expect_nan in ((wv, False), (w, not valid.all())):
+        s = float(vc.vc_norm2(c, up(torch, codes)).cpu()[0])
+        ref = O.norm2(co, codes)
+        if expect_nan:
+            assert math.isnan(s) and math.isnan(ref)
+        else:
+            assert abs(s - ref) <= 4e-6 * ref, (s, ref)
+    dv = float(vc.vc_dot(c, up(torch, wv), up(torch, wb)).cpu()[0])
+    A, B = O.decode64(co, wv), O.decode64(co, wb)
+    scale = float((np.linalg.norm(A, axis=1) * np.linalg.norm(B, axis=1)).sum())
+    assert abs(dv - O.dot(co, wv, wb)) <= 4e-6 * scale
