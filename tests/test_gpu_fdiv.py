@@ -1,9 +1,14 @@
 """GPU parity of the compressed flux divergence (vc_flux_div_tp) against the oracle's Alg.
 (fr_fdiv_comp) in FP64, with the dense operator expanded from the same float32 1D factors.
 
-Tolerance per output: |gpu - oracle| <= 2e-6 sum_{j,c} |D[c ns + j][k]| |X_jp| + 1e-30, i.e. the
-single-precision decode (<= 1e-6 |x| per component) plus single-precision accumulation of the
-3 q terms (< 1e-6 of the sum of their magnitudes).
+Two checks per output k:
+- against the oracle: |gpu - oracle| <= 2e-6 sum_{j,c} |D[c ns + j][k]| ||X_jp|| + 1e-30.  The decode
+  contract bounds each decoded component's error by 1e-6 of the vector's norm (not of the component),
+  so the weight is the norm ||X_jp||; the single-precision accumulation of the 3 q terms adds under
+  1e-6 of the sum of their magnitudes.
+- against the GPU's own decode (vc_decode of the same codes, contracted in FP64): the difference is
+  the kernel's single-precision sum alone, <= (3 q + 2) 2^-24 sum |D| |X^gpu_jpc| + 1e-30.  A wrong
+  element, a stale prefetched group or a reused LDS slot gives an O(1) error here.
 """
 import sys
 
@@ -56,15 +61,21 @@ def _check(torch, c, co, q, npq, ne, seed, label):
     td = torch.from_numpy(d32).to("cuda")
     tW = torch.from_numpy(W.view(np.int64)).to("cuda")
     got = vc.vc_flux_div_tp(c, td, tW).cpu().numpy().astype(np.float64)
+    Xg = vc.vc_decode(c, tW.reshape(-1)).cpu().numpy().astype(np.float64).reshape(ne, q ** 3, npq, 3)
     D = dense(d32)
     ref = O.flux_div(co, D, W)
     X = O.decode64(co, W.reshape(-1)).reshape(ne, q ** 3, npq, 3)
     ns = q ** 3
-    absD = np.abs(D.astype(np.float64)).reshape(3, ns, ns)
-    scale = np.einsum("cjk,ejpc->ekp", absD, np.abs(X), optimize=True)
+    D64 = D.astype(np.float64).reshape(3, ns, ns)
+    absD = np.abs(D64)
+    scale = np.einsum("cjk,ejp->ekp", absD, np.linalg.norm(X, axis=-1), optimize=True)
     ratio = (np.abs(got - ref) / (2e-6 * scale + 1e-30)).max()
-    say(f"{label} q={q} np={npq} ne={ne}: max err/tol {ratio:.3f}")
+    own = np.einsum("cjk,ejpc->ekp", D64, Xg, optimize=True)
+    own_scale = np.einsum("cjk,ejpc->ekp", absD, np.abs(Xg), optimize=True)
+    own_ratio = (np.abs(got - own) / ((3 * q + 2) * 2.0 ** -24 * own_scale + 1e-30)).max()
+    say(f"{label} q={q} np={npq} ne={ne}: max err/tol {ratio:.3f} (oracle), {own_ratio:.3f} (own decode)")
     assert ratio <= 1.0
+    assert own_ratio <= 1.0
     return F, got
 
 

@@ -240,9 +240,11 @@ def test_errhist_full_size(torch_dev):
 
 def test_flux_div_full_size(torch_dev):
     """Alg. (fr_fdiv_comp) on 64^3 p = 4 hexahedra, the benchmark's launch: each persistent
-    workgroup walks many element groups (next-group loads in flight, LDS reused across groups);
-    2,000 sampled elements against the oracle's dense FP64 algorithm, tolerance as in the small
-    cases (2e-6 sum |D| |X|)"""
+    workgroup walks many element groups (next-group loads in flight, LDS reused across groups).
+    The codes are the oracle's encoding of the generated flux.  2,000 sampled elements are checked
+    against the oracle's dense FP64 algorithm (2e-6 sum |D| ||X||: the decode contract bounds a
+    component's error by 1e-6 of the vector's norm) and against the FP64 contraction of the GPU's own
+    decode of the same codes ((3 q + 2) 2^-24 sum |D| |X|: the kernel's single-precision sum alone)"""
     torch = torch_dev
     say("case: full-size flux divergence 64^3 p=4")
     grid, p = (64, 64, 64), 4
@@ -250,26 +252,34 @@ def test_flux_div_full_size(torch_dev):
     ne, ns = grid[0] * grid[1] * grid[2], (p + 1) ** 3
     c, co = vc.codec(), O.codec()
     d32 = np.stack([inputs.fr_derivative_1d(p, 2 * math.pi / gc) for gc in grid]).astype(np.float32)
-    F = inputs.euler_flux_tgv(ne, p, grid=grid, device="cuda")
-    W = vc.vc_encode(c, F.view(-1, 3)).view(ne, ns, npq)
+    F = inputs.euler_flux_tgv(ne, p, grid=grid, device="cuda").cpu().numpy()
+    Wh = O.encode(co, F.reshape(-1, 3)).reshape(ne, ns, npq)
     del F
+    W = torch.from_numpy(Wh.view(np.int64)).to("cuda")
     out = vc.vc_flux_div_tp(c, torch.from_numpy(d32).to("cuda"), W)
     g = np.random.default_rng(64)
     el = np.sort(g.choice(ne, 2000, replace=False))
     # the first and last elements (first and last groups of the walk) always among them
     el = np.unique(np.concatenate([el, [0, 1, ne - 2, ne - 1]]))
     ti = torch.from_numpy(el).to("cuda")
-    Ws = W[ti].cpu().numpy().view(np.uint64)
     got = out[ti].cpu().numpy().astype(np.float64)
-    del W, out
+    Xg = vc.vc_decode(c, W[ti].reshape(-1)).cpu().numpy().astype(np.float64).reshape(len(el), ns, npq, 3)
+    Ws = Wh[el]
+    del W, out, Wh
     eye = np.eye(q, dtype=np.float64)
     dd = d32.astype(np.float64)
     D = np.concatenate([np.kron(eye, np.kron(eye, dd[0])), np.kron(eye, np.kron(dd[1], eye)),
                         np.kron(dd[2], np.kron(eye, eye))]).astype(np.float32)
     ref = O.flux_div(co, D, Ws)
     X = O.decode64(co, Ws.reshape(-1)).reshape(len(el), ns, npq, 3)
-    absD = np.abs(D.astype(np.float64)).reshape(3, ns, ns)
-    scale = np.einsum("cjk,ejpc->ekp", absD, np.abs(X), optimize=True)
+    D64 = D.astype(np.float64).reshape(3, ns, ns)
+    absD = np.abs(D64)
+    scale = np.einsum("cjk,ejp->ekp", absD, np.linalg.norm(X, axis=-1), optimize=True)
     ratio = (np.abs(got - ref) / (2e-6 * scale + 1e-30)).max()
-    say(f"flux div full size: {len(el)} sampled elements, max err/tol {ratio:.3f}")
+    own = np.einsum("cjk,ejpc->ekp", D64, Xg, optimize=True)
+    own_scale = np.einsum("cjk,ejpc->ekp", absD, np.abs(Xg), optimize=True)
+    own_ratio = (np.abs(got - own) / ((3 * q + 2) * 2.0 ** -24 * own_scale + 1e-30)).max()
+    say(f"flux div full size: {len(el)} sampled elements, max err/tol {ratio:.3f} (oracle), "
+        f"{own_ratio:.3f} (own decode)")
     assert ratio <= 1.0
+    assert own_ratio <= 1.0
