@@ -128,6 +128,19 @@ vc_status vc_axpy(const vc_codec* c, float alpha, const uint64_t* a, const uint6
 vc_status vc_dot(const vc_codec* c, const uint64_t* a, const uint64_t* b, size_t n, float* d_out,
                  hipStream_t stream);
 
+/* vc_dot without allocation, for callers that cannot call hipMalloc (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same kernels and the same
+ * result, bit for bit, as vc_dot, with the per-block partial sums in a library-owned device array
+ * of 2048 floats (8 KiB) instead of a hipMallocAsync buffer.  Every n fits (the partials never
+ * exceed 2048); a larger partial count would return VC_ERROR_INVALID_VALUE.  The array is
+ * allocated with the code object, one per device, and held until the process ends; its address
+ * is looked up on the first call on a device (the device current at the call; the stream must
+ * belong to it).  Calls that overlap on one device (two streams, or two host threads) share the
+ * array and race: serialise them.  Each call writes every partial it reads, so nothing needs
+ * clearing between calls. */
+vc_status vc_dot_noalloc(const vc_codec* c, const uint64_t* a, const uint64_t* b, size_t n, float* d_out,
+                         hipStream_t stream);
+
 /* d_out[0] = sum_i |decode(a[i])|^2, from the magnitude field alone (|x_hat| equals the
  * stored magnitude exactly in real arithmetic), single-precision accumulation. */
 vc_status vc_norm2(const vc_codec* c, const uint64_t* a, size_t n, float* d_out, hipStream_t stream);

@@ -53,6 +53,7 @@ _SIGS = {
     "vc_axpy": ([C.POINTER(vc_codec), C.c_float, _vp, _vp, _vp, C.c_size_t, _vp], C.c_int),
     "vc_dot": ([C.POINTER(vc_codec), _vp, _vp, C.c_size_t, _vp, _vp], C.c_int),
     "vc_norm2": ([C.POINTER(vc_codec), _vp, C.c_size_t, _vp, _vp], C.c_int),
+    "vc_dot_noalloc": ([C.POINTER(vc_codec), _vp, _vp, C.c_size_t, _vp, _vp], C.c_int),
     "vc_fused_apply": ([C.POINTER(vc_codec), _vp, C.c_int, C.c_int, _vp, _vp, C.c_size_t, _vp], C.c_int),
     "vc_batch_plan_create": ([C.POINTER(_vp), C.POINTER(vc_codec), C.POINTER(vc_segment), C.c_int, _vp],
                              C.c_int),
@@ -192,6 +193,15 @@ def vc_dot(c: vc_codec, a, b, out=None, stream=None):
     if out is None:
         out = torch.empty(1, dtype=torch.float32, device=a.device)
     _check(lib().vc_dot(C.byref(c), _ptr(a), _ptr(b), a.numel(), _ptr(out), _stream(stream)), "vc_dot")
+    return out
+
+
+def vc_dot_noalloc(c: vc_codec, a, b, out, stream=None):
+    """vc_dot through the allocation-free entry point; ``out`` (one device float) is required."""
+    torch = _torch()
+    _require(out, torch.float32, "vc_dot_noalloc out")
+    _check(lib().vc_dot_noalloc(C.byref(c), _ptr(a), _ptr(b), a.numel(), _ptr(out), _stream(stream)),
+           "vc_dot_noalloc")
     return out
 
 

@@ -200,8 +200,33 @@ vc_status vcx_axpy_dump(const vc_codec* c, float alpha, const uint64_t* a, const
   return logged("vcx_axpy_dump", c, n, axpy_common(c, alpha, a, b, out, n, c32, stream));
 }
 
+// Partial sums of vc_dot_noalloc, one float per reduction block.  reduce_parts(n) never exceeds
+// kScratchSlots, so every n fits.  Each device holds its own copy of the array (8 KiB) until the
+// process ends; in host code `scratch` only names the symbol, so kernels get the device address
+// that hipGetSymbolAddress returns, looked up once per device with that device current.
+constexpr int kScratchSlots = 2048;
+static __device__ __align__(256) float scratch[kScratchSlots];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static float* g_scratch[kMaxDevices];
+
+static vc_status scratch_on_current_device(float** out)
+{
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return VC_ERROR_HIP;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    float* ptr = nullptr;
+    if (hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return VC_ERROR_HIP;
+    g_scratch[dev] = ptr;
+  }
+  *out = g_scratch[dev];
+  return VC_SUCCESS;
+}
+
 static vc_status reduce_common(const vc_codec* c, const uint64_t* a, const uint64_t* b, size_t n, float* d_out,
-                               hipStream_t stream, bool is_dot)
+                               hipStream_t stream, bool is_dot, bool noalloc = false)
 {
   Resolved R;
   vc_status st = resolve(c, &R);
@@ -216,6 +241,12 @@ static vc_status reduce_common(const vc_codec* c, const uint64_t* a, const uint6
   if (!aligned(a, 8) || (is_dot && !aligned(b, 8))) return VC_ERROR_MISALIGNED;
   const int np = reduce_parts(n);
   float* parts = nullptr;
+  if (noalloc) {
+    if (np > kScratchSlots) return VC_ERROR_INVALID_VALUE;
+    st = scratch_on_current_device(&parts);
+    if (st != VC_SUCCESS) return st;
+    return is_dot ? launch_dot(R, a, b, n, parts, np, d_out, stream) : launch_norm2(R, a, n, parts, np, d_out, stream);
+  }
   if (hipMallocAsync((void**)&parts, sizeof(float) * np, stream) != hipSuccess) return VC_ERROR_OUT_OF_MEMORY;
   st = is_dot ? launch_dot(R, a, b, n, parts, np, d_out, stream) : launch_norm2(R, a, n, parts, np, d_out, stream);
   if (hipFreeAsync(parts, stream) != hipSuccess && st == VC_SUCCESS) st = VC_ERROR_HIP;
@@ -238,6 +269,12 @@ vc_status vc_dot(const vc_codec* c, const uint64_t* a, const uint64_t* b, size_t
                  hipStream_t stream)
 {
   return logged("vc_dot", c, n, reduce_common(c, a, b, n, d_out, stream, true));
+}
+
+vc_status vc_dot_noalloc(const vc_codec* c, const uint64_t* a, const uint64_t* b, size_t n, float* d_out,
+                         hipStream_t stream)
+{
+  return logged("vc_dot_noalloc", c, n, reduce_common(c, a, b, n, d_out, stream, true, true));
 }
 
 vc_status vc_norm2(const vc_codec* c, const uint64_t* a, size_t n, float* d_out, hipStream_t stream)

@@ -101,6 +101,10 @@ def test_validation_errors_without_device_work(lib):
     assert lib.vc_axpy(C.byref(ok), 1.0, None, None, None, 0, None) == 0
     # reductions need an output
     assert lib.vc_dot(P, _fake(0x10000), _fake(0x20000), n, None, None) == 1
+    assert lib.vc_dot_noalloc(P, _fake(0x10000), _fake(0x20000), n, None, None) == 1
+    assert lib.vc_dot_noalloc(P, _fake(0x10000), None, n, _fake(0x30000), None) == 1
+    assert lib.vc_dot_noalloc(P, _fake(0x10004), _fake(0x20000), n, _fake(0x30000), None) == 2
+    assert lib.vc_dot_noalloc(P, _fake(0x10000), _fake(0x20000), n, _fake(0x30002), None) == 2
     # baselines
     assert lib.vcb_copy(_fake(0x10000), _fake(0x20008), 64, None) == 2
     assert lib.vcb_axpy_f32(1.0, None, None, None, 0, None) == 0
