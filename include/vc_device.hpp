@@ -115,6 +115,20 @@ VC_DI float fmin_(float a, float b) { return __builtin_fminf(a, b); }
 VC_DI float fmaximum_(float a, float b) { return __builtin_elementwise_maximum(a, b); }
 VC_DI float fminimum_(float a, float b) { return __builtin_elementwise_minimum(a, b); }
 #endif
+// the WIDTH bits of x from bit OFF on, as one v_bfe_u32 (the compiler splits a constant-field
+// extract into a shift and a mask)
+template <int OFF, int WIDTH>
+VC_DI uint32_t ubfe_(uint32_t x)
+{
+  static_assert(OFF >= 0 && WIDTH > 0 && OFF + WIDTH <= 32, "field within 32 bits");
+#ifdef VC_HOST_EMULATION
+  return (x >> OFF) & (WIDTH == 32 ? ~0u : (1u << WIDTH) - 1u);
+#else
+  uint32_t r;
+  asm("v_bfe_u32 %0, %1, %2, %3" : "=v"(r) : "v"(x), "i"(OFF), "i"(WIDTH));
+  return r;
+#endif
+}
 VC_DI uint32_t umax3(uint32_t a, uint32_t b, uint32_t c) { uint32_t m = a > b ? a : b; return m > c ? m : c; }
 
 // ------------------------------------------------------------------ layouts
@@ -190,7 +204,7 @@ VC_DI float decode_mag(uint64_t w)
 {
   static_assert(L::sh_m >= 32, "E and M fields in the high word");
   const uint32_t hi = (uint32_t)(w >> 32);
-  const uint32_t em = (hi >> (L::sh_m - 32)) & ((1u << (L::e + L::m)) - 1u);
+  const uint32_t em = ubfe_<L::sh_m - 32, L::e + L::m>(hi);
   const uint32_t rbits = L::keep_sub ? em << (23 - L::m)                       // the IEEE value itself
                                      : (em << (23 - L::m)) + ((uint32_t)(127 - L::bias) << 23);
   float r = ubits(rbits);
@@ -638,21 +652,24 @@ VC_DI uint64_t encode_vec32(float x, float y, float z, const Params& P)
 // cheaper than the double-float single-precision path.  The hardware FP64
 // reciprocal/rsqrt are ~2^-24 accurate and get one correction step each.
 
-// Level coordinate of atan2(num, den), num, den >= 0: V = Kq atan2/(pi/2) (den >= 0),
-// 2 Kq - that (den < 0), with C = Kq/(pi/2), plus `add` (a multiple of 1/2).
-// mx = max(num, den), mn = min(num, den), swap = num > den.  POLE: mx may be zero (num = den =
-// 0); the denominator is then raised to 2^-1000, so the ratio is 0 and the angle atan2(0, 0) = 0.
-template <bool POLE = false>
-VC_DI double angle_levels64_mm(double mx, double mn, bool swap, bool den_neg, double Kq_half, double C,
-                               double add = 0.0)
+// Level coordinate of an angle a in [0, pi] from the tangent of its half, t = num/den in [0, 1]:
+// a' = 2 atan(t) in [0, pi/2], and a = a' (reflect false) or pi - a' (reflect true).  Kq is the
+// level count of a quarter turn, so a = pi is 2 Kq levels, and C2 = 2 (2 Kq)/pi converts atan to
+// levels.  Above t = tan(pi/8) the ratio is reduced, atan(t) = pi/4 + atan((num - den)/(num + den)),
+// so the polynomial sees |b| <= tan(pi/8).  Returns add + V (reflect false) or add + 2 Kq - V
+// (reflect true), V = [R] Kq + C2 atan(b), with add = 1/2 (HALF) or 0; the offsets are exact.
+// POLE: den may be zero (num = den = 0); it is raised to 2^-1000, so the ratio is 0.
+template <bool POLE, bool HALF>
+VC_DI double half_angle_levels64(double num, double den, bool reflect, double Kq, double C2)
 {
+  constexpr double add = HALF ? 0.5 : 0.0;
   constexpr double T8 = 0.41421356237309503;      // tan(pi/8)
-  const bool R = mn > T8 * mx;
-  // (nu, de) = R ? (mn - mx, mn + mx) : (mn, mx), as FMAs with a 0/1 factor (each one rounding,
-  // or exact when the factor is 0)
+  const bool R = num > T8 * den;
+  // (nu, de) = R ? (num - den, num + den) : (num, den), as FMAs with a 0/1 factor (each one
+  // rounding, or exact when the factor is 0)
   const double Rd = R ? 1.0 : 0.0;
-  const double nu = fma64_(-Rd, mx, mn);
-  double de = fma64_(Rd, mn, mx);                 // >= mx > 0 unless num = den = 0
+  const double nu = fma64_(-Rd, den, num);
+  double de = fma64_(Rd, num, den);
   if constexpr (POLE) de = __builtin_fmax(de, 0x1p-1000);
   const double rc = rcp64_(de);
   double b = nu * rc;
@@ -662,19 +679,9 @@ VC_DI double angle_levels64_mm(double mx, double mn, bool swap, bool den_neg, do
 #pragma unroll
   for (int i = VC_ATAN_R64_DEG - 1; i >= 0; i--) Rp = fma64_(Rp, s2, VC_ATAN_R64[i]);
   const double at = fma64_(b, s2 * Rp, b);        // atan(b)
-  // octant: atan2 = k pi/4 + sgn atan(b) with k = k0 + sgn [R], k0 = 2 if swapped, else 4 if
-  // den < 0, else 0, and sgn = -1 when exactly one of (den < 0, swapped) holds; all in doubles
-  // (k, k Kq_half + add and sgn atan(b) are exact)
-  const bool neg = den_neg != swap;
-  const double sgn = neg ? -1.0 : 1.0;
-  const double k0 = swap ? 2.0 : (den_neg ? 4.0 : 0.0);
-  const double k = fma64_(sgn, Rd, k0);
-  return fma64_(C, sgn * at, fma64_(k, Kq_half, add));
-}
-
-VC_DI double angle_levels64(double num, double den, bool den_neg, double Kq_half, double C, double add = 0.0)
-{
-  return angle_levels64_mm<false>(fmax64_nn(num, den), fmin64_nn(num, den), num > den, den_neg, Kq_half, C, add);
+  const double V = fma64_(C2, at, Rd * Kq);
+  if constexpr (HALF) return reflect ? fma64_(2.0, Kq, add) - V : add + V;
+  else return reflect ? 2.0 * Kq - V : V;         // (a -0 from V is harmless: levels are floored)
 }
 
 // Companded level distance from the centre: K h(q/K) for q = K |u| >= 0.
@@ -707,12 +714,10 @@ VC_DI double compand64(double q, double invK, const Params& P)
 template <class L, int MODE>
 VC_DI uint64_t encode_vec64(float x, float y, float z, const Params& P)
 {
-  // max and min of |x|, |y| (for theta's octant reduction) and |z|, taken in single precision and
-  // converted exactly; the squares are exact in FP64.  The signs come from the inputs below.  The
-  // max and min propagate a NaN, so that a NaN in x or y reaches r^2 and the non-finite test.
-  const float ax = __builtin_fabsf(x), ay = __builtin_fabsf(y);
-  const double Mx = (double)fmaximum_(ax, ay), Mn = (double)fminimum_(ax, ay), Z = (double)__builtin_fabsf(z);
-  const double R2 = fma64_(Mx, Mx, Mn * Mn);      // rho^2, one rounding
+  // |x|, |y|, |z| converted exactly; the squares are exact in FP64.  The signs come from the
+  // inputs below.  A NaN in any component reaches r^2 and the non-finite test.
+  const double X = (double)__builtin_fabsf(x), Y = (double)__builtin_fabsf(y), Z = (double)__builtin_fabsf(z);
+  const double R2 = fma64_(X, X, Y * Y);          // rho^2, one rounding
   // r^2, two roundings (2^-52).  A finite float squares to below 2^256, so r^2 is finite exactly
   // when every component is.  The squares of nonzero floats are at least 2^-298, so raising r^2
   // to 2^-1000 changes only the zero vector, whose norm 2^-500 then flushes to the zero code
@@ -760,16 +765,19 @@ VC_DI uint64_t encode_vec64(float x, float y, float z, const Params& P)
                      : ((uint64_t)(uint32_t)E << L::sh_e) | ((uint64_t)Mfield << L::sh_m);
   }
 
-  // ---- rho = sqrt(x^2 + y^2) to ~2^-47 (R2 + 2^-1000 == R2 unless R2 == 0)
+  // ---- rho = sqrt(x^2 + y^2) to ~2^-47 (R2 + 2^-1000 == R2 unless R2 == 0).  With z = 0 this
+  //      is the same computation on the same value as r above, so rho == r exactly there.
   const double R2g = R2 + 0x1p-1000;
   const double yR = rsq64_(R2g);
   const double p0 = R2 * yR;
   const double rho = fma64_(fma64_(-p0, p0, R2), 0.5 * yR, p0);
 
-  // ---- theta: |Q| = Kt |theta|/pi; n = base + floor(+-|Q| (+1/2 if n_theta_max is even))
+  // ---- theta: |Q| = Kt |theta|/pi; n = base + floor(+-|Q| (+1/2 if n_theta_max is even)).
+  //      The half angle of |theta| in [0, pi] has the tangent |y| / (rho + x): from x >= 0,
+  //      |y| / (rho + |x|) gives theta' = atan2(|y|, |x|), reflected (pi - theta') for x < 0.
+  //      At the pole (x = y = 0) the ratio is 0/0, made 0: theta = atan2(0, 0) = 0 (R12).
   const bool yneg = y < 0.0f, xneg = x < 0.0f, zneg = z < 0.0f;
-  // at the pole (x = y = 0) the angle is atan2(0, 0) = 0 and the level the base level (R12)
-  double Q = angle_levels64_mm<true>(Mx, Mn, ay > ax, xneg, 0.25 * P.Kt64, P.Ct64);
+  double Q = half_angle_levels64<true, false>(Y, rho + X, xneg, 0.5 * P.Kt64, 2.0 * P.Ct64);
   if ((MODE == TANH || MODE == COS) && P.comp_t) Q = compand64<MODE>(Q, P.invKt64, P);
   uint32_t nth;
   if (MODE == FRAC) {
@@ -782,15 +790,17 @@ VC_DI uint64_t encode_vec64(float x, float y, float z, const Params& P)
     nth = yneg ? (uint32_t)((int)P.base_t - 1 - f) : (uint32_t)((int)P.base_t + f);
   }
 
-  // ---- phi: V = n_phi_max phi/pi; n = floor(V + 1/2)
+  // ---- phi: V = n_phi_max phi/pi; n = floor(V + 1/2).  The half angle of phi' = atan2(rho, |z|)
+  //      has the tangent rho / (r + |z|) in [0, 1] (r + |z| >= r > 0); phi = pi - phi' for z < 0.
+  //      At z = 0, rho == r, so the ratio is exactly 1 and phi exactly pi/2 (the tie of R3).
   uint32_t nph;
   if ((MODE == TANH || MODE == COS) && P.comp_p) {
-    const double V = angle_levels64(rho, Z, zneg, 0.25 * P.Np64, P.Cp64);
+    const double V = half_angle_levels64<false, false>(rho, r + Z, zneg, 0.5 * P.Np64, 2.0 * P.Cp64);
     const double Qc = V - 0.5 * P.Np64;           // (n_phi_max/2) u_phi, exact zero at phi = pi/2
     const double m = compand64<MODE>(__builtin_fabs(Qc), P.invKc64, P);
     nph = (uint32_t)((int)((P.nmax_p + 1u) / 2u) + (int)floor64_(Qc < 0 ? -m : m));
   } else {
-    const double Vh = angle_levels64(rho, Z, zneg, 0.25 * P.Np64, P.Cp64, 0.5);   // V + 1/2
+    const double Vh = half_angle_levels64<false, true>(rho, r + Z, zneg, 0.5 * P.Np64, 2.0 * P.Cp64);   // V + 1/2
     nph = (uint32_t)(int)Vh;                      // Vh >= 0: truncation is the floor
   }
 

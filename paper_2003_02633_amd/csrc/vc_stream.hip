@@ -250,7 +250,7 @@ static constexpr uint32_t pack_cfg(int block, int vpt, int nt)
 {
   return (uint32_t)block | (uint32_t)vpt << 12 | (uint32_t)nt << 20;
 }
-static std::atomic<uint32_t> g_axpy_cfg[2] = {pack_cfg(512, 1, 1) /* PREC_F32 */, pack_cfg(512, 2, 1) /* PREC_F64 */};
+static std::atomic<uint32_t> g_axpy_cfg[2] = {pack_cfg(512, 1, 1) /* PREC_F32 */, pack_cfg(256, 4, 1) /* PREC_F64 */};
 
 StreamCfg stream_cfg(int prec)
 {

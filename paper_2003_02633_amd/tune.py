@@ -22,7 +22,21 @@ DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning
 CONFIGS = [(b, v, t) for b in (128, 256, 512) for v in (2, 4, 8) for t in (1, 0) if v < 8 or b >= 256]
 
 
-def sweep(n: int = 1 << 27, precision: str = "f64", steps: int = 10, warmup: int = 2, log=print):
+def _settle(torch, fn, ms: float):
+    """back-to-back untimed calls for `ms` of wall time: the GPU clocks drop within milliseconds
+    of idle and take tens of milliseconds of load to come back, so each configuration is timed
+    only after its own warm-up by time"""
+    import time
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while (time.perf_counter() - t0) * 1e3 < ms:
+        for _ in range(8):
+            fn()
+        torch.cuda.synchronize()
+
+
+def sweep(n: int = 1 << 27, precision: str = "f64", steps: int = 20, settle_ms: float = 150.0, log=print):
     import torch
 
     import paper_2003_02633_amd as vc
@@ -38,9 +52,7 @@ def sweep(n: int = 1 << 27, precision: str = "f64", steps: int = 10, warmup: int
     try:
         for (blk, vpt, nt) in CONFIGS:
             vc.set_stream_config(blk, vpt, nt, precision)
-            for _ in range(warmup):
-                vc.vc_axpy(c, 0.7, a, b, out)
-            torch.cuda.synchronize()
+            _settle(torch, lambda: vc.vc_axpy(c, 0.7, a, b, out), settle_ms)
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
             for _ in range(steps):

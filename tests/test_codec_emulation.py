@@ -114,8 +114,11 @@ def test_emulated_encode_matches_oracle(layout, mode, kw):
         res = classify(co, xyz, dev)
         assert res["other"] == 0, f"{name}:\n" + describe_bad(co, xyz, dev, res)
         # within-window level differences are rare (design error ~1e-4 level units) on the drawn
-        # workloads; the non-finite grid is mostly axis and diagonal directions, on level ties
-        if name != "nonfinite":
+        # workloads.  The non-finite grid and the crafted vectors are mostly axis and 45-degree
+        # directions; for some level counts (fractional split, n_max = 2 mod 4) the diagonals lie
+        # exactly on a level tie, which the encoder (angles from their half-angle tangents, exact
+        # on the axes only) may resolve either way inside the window
+        if name not in ("nonfinite", "crafted"):
             assert res["pm1_theta"] + res["pm1_phi"] <= max(2, 2e-3 * res["n"]), res
 
 
