@@ -61,7 +61,7 @@ VC_DI float ldexp_(float x, int e) { return ldexpf(x, e); }
 VC_DI float floor_(float x) { return floorf(x); }
 VC_DI float fma_(float a, float b, float c) { return fmaf(a, b, c); }
 VC_DI float log2_(float x) { return log2f(x); }
-VC_DI float asin_(float x) { return asinf(x); }
+VC_DI float sqrt_(float x) { return sqrtf(x); }
 #else
 VC_DI uint32_t fbits(float f) { return __float_as_uint(f); }
 VC_DI float ubits(uint32_t u) { return __uint_as_float(u); }
@@ -74,7 +74,7 @@ VC_DI float ldexp_(float x, int e) { return __builtin_amdgcn_ldexpf(x, e); }
 VC_DI float floor_(float x) { return __builtin_floorf(x); }
 VC_DI float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 VC_DI float log2_(float x) { return __builtin_amdgcn_logf(x); }     // v_log_f32 (log2)
-VC_DI float asin_(float x) { return asinf(x); }
+VC_DI float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }   // v_sqrt_f32
 #endif
 #ifdef VC_HOST_EMULATION
 VC_DI uint64_t dbits(double d) { uint64_t u; memcpy(&u, &d, 8); return u; }
@@ -91,8 +91,9 @@ VC_DI double rcp64_(double x) { return __builtin_amdgcn_rcp(x); }   // v_rcp_f64
 VC_DI double floor64_(double x) { return __builtin_floor(x); }
 VC_DI double fma64_(double a, double b, double c) { return __builtin_fma(a, b, c); }
 #endif
-// max / min of two doubles that are never NaN: the plain v_max_f64 / v_min_f64, without the
-// operand canonicalisation the compiler adds for fmax / fmin in IEEE mode
+// max / min of two doubles that are never signalling NaNs: the plain v_max_f64 / v_min_f64,
+// without the operand canonicalisation the compiler adds for fmax / fmin in IEEE mode.  A quiet
+// NaN in the first operand gives the second (as the hardware's IEEE minNum/maxNum does).
 #ifdef VC_HOST_EMULATION
 VC_DI double fmax64_nn(double a, double b) { return a > b ? a : b; }
 VC_DI double fmin64_nn(double a, double b) { return a < b ? a : b; }
@@ -263,37 +264,64 @@ VC_DI float times_rcp(float x, float h, float l)
   return x * h;
 }
 
-// Angles of the levels in revolutions (Eq. a_inv, §2.5 for the companded maps):
-// theta_hat/(2 pi) = n/n_max - 1/2, phi_hat/(2 pi) = n/(2 n_max) for uniform levels.
+// Angles of the levels in revolutions (Eq. a_inv; §2.5 for the tanh map):
+// theta_hat/(2 pi) = n/n_max - 1/2, phi_hat/(2 pi) = n/(2 n_max) for uniform levels.  (The
+// cosine map has no call here: its sines and cosines are algebraic in the levels, cos_map_trig.)
 template <int MODE>
 VC_DI void level_revs(uint32_t nth, uint32_t nph, const Params& P, float& rev_t, float& rev_p)
 {
+  static_assert(MODE != COS, "the cosine map decodes through cos_map_trig");
   // theta: (n - n_max/2)/n_max = n/n_max - 1/2, one FMA with the single-product reciprocal;
   // the fractional split forms n - n_max/2 exactly and takes the double-float reciprocal
   auto theta_rev = [&]() {
     if (MODE == FRAC) return times_rcp<MODE>((float)nth - P.half_t, P.rt_h, P.rt_l);
     return fma_((float)nth, P.rt_h, -0.5f);
   };
-  if (MODE == TANH || MODE == COS) {
-    const float hh_t = (2.0f * (float)nth - (float)P.nmax_t) / (float)P.nmax_t;
-    const float hh_p = (2.0f * (float)nph - (float)P.nmax_p) / (float)P.nmax_p;
-    float ut = hh_t, up = hh_p;
-    if (MODE == TANH) {
-      // u = atanh(c h)/gamma = ln((1+ch)/(1-ch)) / (2 gamma)
-      if (P.comp_t) { float a = P.cgam * hh_t; ut = 0.34657359f * P.inv_gam * log2_((1.0f + a) / (1.0f - a)); }
-      if (P.comp_p) { float a = P.cgam * hh_p; up = 0.34657359f * P.inv_gam * log2_((1.0f + a) / (1.0f - a)); }
-    } else {
-      // u = (2/pi) asin(h)
-      if (P.comp_t) ut = 0.63661977f * asin_(hh_t);
-      if (P.comp_p) up = 0.63661977f * asin_(hh_p);
-    }
-    rev_t = 0.5f * ut;
-    rev_p = 0.25f * (up + 1.0f);
-    if (!P.comp_t) rev_t = theta_rev();
-    if (!P.comp_p) rev_p = times_rcp<MODE>((float)nph, P.rp_h, P.rp_l);
+  if (MODE == TANH) {
+    // the centred level coordinate h = 2 n/n_max - 1 maps back to u = atanh(c h)/gamma
+    // (c = tanh gamma), taken as (log2(1 + c h) - log2(1 - c h)) ln 2/(2 gamma): two hardware
+    // logarithms, no division; theta_hat = pi u, phi_hat = pi (u + 1)/2
+    auto inv = [&](uint32_t n, float two_over_nmax) {
+      const float a = P.cgam * fma_((float)n, two_over_nmax, -1.0f);
+      return (log2_(1.0f + a) - log2_(1.0f - a)) * (0.34657359f * P.inv_gam);
+    };
+    if (P.comp_t) rev_t = 0.5f * inv(nth, 2.0f * P.rt_h);
+    else rev_t = theta_rev();
+    if (P.comp_p) rev_p = fma_(0.25f, inv(nph, 4.0f * P.rp_h), 0.25f);
+    else rev_p = times_rcp<MODE>((float)nph, P.rp_h, P.rp_l);
   } else {
     rev_t = theta_rev();
     rev_p = times_rcp<MODE>((float)nph, P.rp_h, P.rp_l);
+  }
+}
+
+// Sines and cosines of the decoded angles under the cosine map (§2.5): with the centred level
+// coordinates h = 2 n_t/N_t - 1 and g = 2 n_p/N_p - 1 (N the level counts), theta_hat = 2 asin(h)
+// and phi_hat = pi/2 + asin(g), so
+//   cos theta = 1 - 2 h^2,  sin theta = 2 h sqrt(1 - h^2),  cos phi = -g,  sin phi = sqrt(1 - g^2),
+// where 1 - h^2 = 4 n (N - n)/N^2 comes from the exact factors n and N - n (no cancellation at
+// the ends, and sin phi = 0 exactly at the poles).  An angle outside the companding mask takes
+// the uniform levels and the hardware sine and cosine.
+VC_DI void cos_map_trig(uint32_t nth, uint32_t nph, const Params& P, float& st, float& ct, float& sp, float& cp)
+{
+  if (P.comp_t) {
+    const float n = (float)nth, m = (float)(P.nmax_t - nth);
+    const float h = fma_(n, 2.0f * P.rt_h, -1.0f);
+    ct = fma_(-2.0f * h, h, 1.0f);
+    st = (4.0f * P.rt_h) * h * sqrt_(n * m);
+  } else {
+    const float rev = fma_((float)nth, P.rt_h, -0.5f);
+    st = sin_rev(rev);
+    ct = cos_rev(rev);
+  }
+  if (P.comp_p) {
+    const float n = (float)nph, m = (float)(P.nmax_p - nph);
+    cp = fma_(n, -4.0f * P.rp_h, 1.0f);
+    sp = (4.0f * P.rp_h) * sqrt_(n * m);
+  } else {
+    const float rev = (float)nph * P.rp_h;
+    sp = sin_rev(rev);
+    cp = cos_rev(rev);
   }
 }
 
@@ -304,10 +332,17 @@ VC_DI void decode_vec(uint64_t w, const Params& P, float& ox, float& oy, float& 
   float r;
   uint32_t nth, nph;
   decode_fields<L, MODE>(w, P, r, nth, nph);
-  float rev_t, rev_p;
-  level_revs<MODE>(nth, nph, P, rev_t, rev_p);
-  const float st = sin_rev(rev_t), ct = cos_rev(rev_t);
-  const float sp = sin_rev(rev_p), cp = cos_rev(rev_p);
+  float st, ct, sp, cp;
+  if constexpr (MODE == COS) {
+    cos_map_trig(nth, nph, P, st, ct, sp, cp);
+  } else {
+    float rev_t, rev_p;
+    level_revs<MODE>(nth, nph, P, rev_t, rev_p);
+    st = sin_rev(rev_t);
+    ct = cos_rev(rev_t);
+    sp = sin_rev(rev_p);
+    cp = cos_rev(rev_p);
+  }
   const float rs = r * sp;
   ox = rs * ct;
   oy = rs * st;
@@ -318,23 +353,57 @@ VC_DI void decode_vec(uint64_t w, const Params& P, float& ox, float& oy, float& 
 //   r_a r_b (sin phi_a sin phi_b cos(theta_a - theta_b) + cos phi_a cos phi_b),
 // five hardware sine/cosine evaluations instead of the eight of two decodes.  For uniform theta
 // levels the difference of the angles is formed from the exact difference of the level counts.
+// The cosine map, whose decode needs no sine or cosine, takes the Cartesian product.
 template <class L, int MODE>
 VC_DI float dot_pair(uint64_t wa, uint64_t wb, const Params& P)
 {
-  float ra, rb;
-  uint32_t ta, pa, tb, pb;
-  decode_fields<L, MODE>(wa, P, ra, ta, pa);
-  decode_fields<L, MODE>(wb, P, rb, tb, pb);
-  float rta, rpa, rtb, rpb, drev;
-  level_revs<MODE>(ta, pa, P, rta, rpa);
-  level_revs<MODE>(tb, pb, P, rtb, rpb);
-  if (MODE == PLAIN || MODE == FRAC || ((MODE == TANH || MODE == COS) && !P.comp_t))
-    drev = times_rcp<MODE>((float)((int)ta - (int)tb), P.rt_h, P.rt_l);   // |ta - tb| < 2^24: exact
-  else
-    drev = rta - rtb;
-  const float sa = sin_rev(rpa), ca = cos_rev(rpa), sb = sin_rev(rpb), cb = cos_rev(rpb);
-  return (ra * rb) * fma_(sa * sb, cos_rev(drev), ca * cb);
+  if constexpr (MODE == COS) {
+    float ax, ay, az, bx, by, bz;
+    decode_vec<L, MODE>(wa, P, ax, ay, az);
+    decode_vec<L, MODE>(wb, P, bx, by, bz);
+    return fma_(ax, bx, fma_(ay, by, az * bz));
+  } else {
+    float ra, rb;
+    uint32_t ta, pa, tb, pb;
+    decode_fields<L, MODE>(wa, P, ra, ta, pa);
+    decode_fields<L, MODE>(wb, P, rb, tb, pb);
+    float rta, rpa, rtb, rpb, drev;
+    level_revs<MODE>(ta, pa, P, rta, rpa);
+    level_revs<MODE>(tb, pb, P, rtb, rpb);
+    if (MODE == PLAIN || MODE == FRAC || (MODE == TANH && !P.comp_t))
+      drev = times_rcp<MODE>((float)((int)ta - (int)tb), P.rt_h, P.rt_l);   // |ta - tb| < 2^24: exact
+    else
+      drev = rta - rtb;
+    const float sa = sin_rev(rpa), ca = cos_rev(rpa), sb = sin_rev(rpb), cb = cos_rev(rpb);
+    return (ra * rb) * fma_(sa * sb, cos_rev(drev), ca * cb);
+  }
 }
+
+// The companding mask (which angles the map applies to) is a run-time field.  A kernel runs its
+// body as with_compand_mask<MODE>(P, body): when both angles are companded (the default) the body
+// gets a copy of the parameters whose mask is a compile-time constant, so its per-vector code has
+// no branches on it; other masks take the run-time tests.
+template <int MODE, class F>
+VC_DI void with_compand_mask(const Params& P, F&& body)
+{
+  if constexpr (MODE == TANH || MODE == COS) {
+    if (P.comp_t && P.comp_p) {
+      Params Q = P;
+      Q.comp_t = 1u;
+      Q.comp_p = 1u;
+      body(static_cast<const Params&>(Q));
+    } else {
+      body(P);
+    }
+  } else {
+    body(P);
+  }
+}
+
+// Degree of the tanh map's polynomial an encoder instantiation evaluates (TDEG of encode_vec): the
+// host fits the smallest degree it needs (8 up to gamma ~0.55, at most 15; higher coefficients
+// zero) and launches the instantiation of this bound that covers it.
+inline constexpr int tanh_tdeg(int fitted) { return fitted <= 8 ? 8 : 15; }
 
 // ------------------------------------------------------------------ encode helpers
 
@@ -483,8 +552,9 @@ VC_DI void compand_levels(float qh, float ql, float K, const Params& P, float& o
   if (MODE == TANH) {
     const float u = qh * (1.0f / K);
     const float v = u * u;
-    float acc = P.w[P.wdeg];
-    for (int i = P.wdeg - 1; i >= 0; i--) acc = fma_(acc, v, P.w[i]);
+    float acc = P.w[7];                          // degree 7 (the host fits P.w at that degree)
+#pragma unroll
+    for (int i = 6; i >= 0; i--) acc = fma_(acc, v, P.w[i]);
     const float d = qh * acc;                    // |Q| w, <= ~0.09 |Q|
     oh = qh + d;
     ol = ((qh - oh) + d) + ql * (1.0f + acc);
@@ -685,14 +755,18 @@ VC_DI double half_angle_levels64(double num, double den, bool reflect, double Kq
 }
 
 // Companded level distance from the centre: K h(q/K) for q = K |u| >= 0.
-template <int MODE>
+template <int MODE, int TDEG = 15>
 VC_DI double compand64(double q, double invK, const Params& P)
 {
   const double u = q * invK;
   const double v = u * u;
-  if (MODE == TANH) {                             // h(u)/u = W(u^2), fitted per gamma on the host
-    double acc = P.w64[P.wdeg64];
-    for (int i = P.wdeg64 - 1; i >= 0; i--) acc = fma64_(acc, v, P.w64[i]);
+  if (MODE == TANH) {
+    // h(u)/u = W(u^2), fitted per gamma on the host to the degree it needs (at most 15, and at
+    // most TDEG here; the coefficients above the fitted degree are zero)
+    static_assert(TDEG >= 1 && TDEG <= 15, "tanh polynomial degree");
+    double acc = P.w64[TDEG];
+#pragma unroll
+    for (int i = TDEG - 1; i >= 0; i--) acc = fma64_(acc, v, P.w64[i]);
     return q * acc;
   }
   // cosine map: h(u) = sin(pi u / 2) = (pi/2) u S(x^2), x = pi u / 2 (Taylor, |x| <= pi/2)
@@ -711,8 +785,13 @@ VC_DI double compand64(double q, double invK, const Params& P)
   return q * (1.5707963267948966 * S);
 }
 
-template <class L, int MODE>
-VC_DI uint64_t encode_vec64(float x, float y, float z, const Params& P)
+// Branch-free part of the FP64-assisted encoder: the code of (x, y, z), and `exact` set where the
+// magnitude lies within 2^-44 of a rounding midpoint (or, for layouts that keep subnormals, in the
+// lowest binade), where the code's E and M fields are to be replaced by encode64_exact_fix.  Every
+// other case, non-finite input, underflow and saturation included, comes out final, by selects,
+// so the only branch of encode_vec64 is the rare exact one.
+template <class L, int MODE, int TDEG = 15>
+VC_DI uint64_t encode_vec64_fast(float x, float y, float z, const Params& P, bool& exact)
 {
   // |x|, |y|, |z| converted exactly; the squares are exact in FP64.  The signs come from the
   // inputs below.  A NaN in any component reaches r^2 and the non-finite test.
@@ -722,9 +801,11 @@ VC_DI uint64_t encode_vec64(float x, float y, float z, const Params& P)
   // when every component is.  The squares of nonzero floats are at least 2^-298, so raising r^2
   // to 2^-1000 changes only the zero vector, whose norm 2^-500 then flushes to the zero code
   // below like any norm under the smallest magnitude (through the exact path, where the layout
-  // keeps subnormals).
+  // keeps subnormals).  For non-finite input the arithmetic below runs on infinities and NaNs
+  // and its result is replaced by the reserved code at the end; the level conversions clamp
+  // their operand first, so they stay defined.
   const double S0 = fma64_(Z, Z, R2);
-  if (!(S0 < __builtin_huge_val())) return L::reserved;  // non-finite input (the test is false for NaN)
+  const bool bad = !(S0 < __builtin_huge_val());  // non-finite input (the test is false for NaN)
   const double S = fmax64_nn(S0, 0x1p-1000);
 
   // ---- magnitude: r to ~2^-47 (rsqrt seed + one Newton step), nearest-even at 1+mr bits
@@ -742,28 +823,13 @@ VC_DI uint64_t encode_vec64(float x, float y, float z, const Params& P)
   constexpr uint64_t rb_lo = (uint64_t)(1024 - L::bias) << 52;
   constexpr uint64_t rb_hi = (uint64_t)(1024 - L::bias + L::emax) << 52;
   if (L::keep_sub) amb = amb || rb < rb_lo + (1ull << 52);   // E <= 1: subnormal codes, exact path
-  uint64_t em;                                    // the code's E and M fields in place
-  if (!amb) {
-    if (rb < rb_lo) return 0ull;                  // underflow flushes to the zero code
-    // the FP64 exponent and fraction fields of rb moved to the code's E|M position, with the
-    // exponent re-biased (modulo 2^64 the bits above the field drop out)
-    constexpr int k = L::sh_e - 52;
-    static_assert(k > 0, "code exponent field above bit 52");
-    em = rb >= rb_hi ? L::saturated : (rb << k) - ((uint64_t)(1023 - L::bias) << L::sh_e);
-  } else {
-    uint32_t j;
-    int g, e_r;
-    uint32_t Mfield;
-    exact_norm_round(x, y, z, L::mr + 1, L::keep_sub, j, g);
-    if constexpr (L::trunc) { j >>= L::mr - L::m; g += L::mr - L::m; }
-    if (j >= (1u << L::m)) { e_r = g + L::m; Mfield = j - (1u << L::m); }
-    else { e_r = -L::bias; Mfield = j; }
-    int E = e_r + L::bias;
-    if (E < 1 && !(L::keep_sub && E == 0)) return 0ull;   // underflow flushes to the zero code
-    if (L::keep_sub && E == 0 && Mfield == 0u) return 0ull;
-    em = E > L::emax ? L::saturated                        // saturate, angles kept
-                     : ((uint64_t)(uint32_t)E << L::sh_e) | ((uint64_t)Mfield << L::sh_m);
-  }
+  exact = amb && !bad;
+  const bool under = rb < rb_lo;                  // underflow flushes to the zero code
+  // the FP64 exponent and fraction fields of rb moved to the code's E|M position, with the
+  // exponent re-biased (modulo 2^64 the bits above the field drop out); saturated above the range
+  constexpr int k = L::sh_e - 52;
+  static_assert(k > 0, "code exponent field above bit 52");
+  const uint64_t em = rb >= rb_hi ? L::saturated : (rb << k) - ((uint64_t)(1023 - L::bias) << L::sh_e);
 
   // ---- rho = sqrt(x^2 + y^2) to ~2^-47 (R2 + 2^-1000 == R2 unless R2 == 0).  With z = 0 this
   //      is the same computation on the same value as r above, so rho == r exactly there.
@@ -778,7 +844,8 @@ VC_DI uint64_t encode_vec64(float x, float y, float z, const Params& P)
   //      At the pole (x = y = 0) the ratio is 0/0, made 0: theta = atan2(0, 0) = 0 (R12).
   const bool yneg = y < 0.0f, xneg = x < 0.0f, zneg = z < 0.0f;
   double Q = half_angle_levels64<true, false>(Y, rho + X, xneg, 0.5 * P.Kt64, 2.0 * P.Ct64);
-  if ((MODE == TANH || MODE == COS) && P.comp_t) Q = compand64<MODE>(Q, P.invKt64, P);
+  if ((MODE == TANH || MODE == COS) && P.comp_t) Q = compand64<MODE, TDEG>(Q, P.invKt64, P);
+  Q = fmin64_nn(Q, 0x1p30);                       // a (quiet) NaN or infinity (non-finite input) -> 2^30
   uint32_t nth;
   if (MODE == FRAC) {
     const double Qs = yneg ? -Q : Q;
@@ -797,25 +864,61 @@ VC_DI uint64_t encode_vec64(float x, float y, float z, const Params& P)
   if ((MODE == TANH || MODE == COS) && P.comp_p) {
     const double V = half_angle_levels64<false, false>(rho, r + Z, zneg, 0.5 * P.Np64, 2.0 * P.Cp64);
     const double Qc = V - 0.5 * P.Np64;           // (n_phi_max/2) u_phi, exact zero at phi = pi/2
-    const double m = compand64<MODE>(__builtin_fabs(Qc), P.invKc64, P);
+    const double m = fmin64_nn(compand64<MODE, TDEG>(__builtin_fabs(Qc), P.invKc64, P), 0x1p30);
     nph = (uint32_t)((int)((P.nmax_p + 1u) / 2u) + (int)floor64_(Qc < 0 ? -m : m));
   } else {
-    const double Vh = half_angle_levels64<false, true>(rho, r + Z, zneg, 0.5 * P.Np64, 2.0 * P.Cp64);   // V + 1/2
+    const double Vh = fmin64_nn(half_angle_levels64<false, true>(rho, r + Z, zneg, 0.5 * P.Np64, 2.0 * P.Cp64),
+                                0x1p30);          // V + 1/2
     nph = (uint32_t)(int)Vh;                      // Vh >= 0: truncation is the floor
   }
 
-  if (MODE == FRAC) return em | ((uint64_t)nph * (uint64_t)P.T + (uint64_t)nth);
-  // the E and M fields lie in the high word; n_phi straddles the two words
-  const uint32_t lo = nth | (nph << L::t);
-  const uint32_t hi = (uint32_t)(em >> 32) | (nph >> (32 - L::t));
-  return ((uint64_t)hi << 32) | lo;
+  uint64_t w;
+  if (MODE == FRAC) {
+    w = em | ((uint64_t)nph * (uint64_t)P.T + (uint64_t)nth);
+  } else {
+    // the E and M fields lie in the high word; n_phi straddles the two words
+    const uint32_t lo = nth | (nph << L::t);
+    const uint32_t hi = (uint32_t)(em >> 32) | (nph >> (32 - L::t));
+    w = ((uint64_t)hi << 32) | lo;
+  }
+  w = under && !exact ? 0ull : w;                // (the exact fix needs the angle fields)
+  return bad ? L::reserved : w;
+}
+
+// The code's E and M fields from the exact norm (nearest-even at 1+mr bits, decided by integer
+// arithmetic), merged with the angle fields of `w` (a code of the same vector): the cases
+// encode_vec64_fast leaves to it.  Underflow gives the zero code, overflow saturates.
+template <class L>
+VC_DI uint64_t encode64_exact_fix(float x, float y, float z, uint64_t w)
+{
+  uint32_t j;
+  int g, e_r;
+  uint32_t Mfield;
+  exact_norm_round(x, y, z, L::mr + 1, L::keep_sub, j, g);
+  if constexpr (L::trunc) { j >>= L::mr - L::m; g += L::mr - L::m; }
+  if (j >= (1u << L::m)) { e_r = g + L::m; Mfield = j - (1u << L::m); }
+  else { e_r = -L::bias; Mfield = j; }
+  const int E = e_r + L::bias;
+  if (E < 1 && !(L::keep_sub && E == 0)) return 0ull;   // underflow flushes to the zero code
+  if (L::keep_sub && E == 0 && Mfield == 0u) return 0ull;
+  const uint64_t em = E > L::emax ? L::saturated                        // saturate, angles kept
+                                  : ((uint64_t)(uint32_t)E << L::sh_e) | ((uint64_t)Mfield << L::sh_m);
+  return (w & ((1ull << L::sh_m) - 1ull)) | em;
+}
+
+template <class L, int MODE, int TDEG = 15>
+VC_DI uint64_t encode_vec64(float x, float y, float z, const Params& P)
+{
+  bool exact;
+  const uint64_t w = encode_vec64_fast<L, MODE, TDEG>(x, y, z, P, exact);
+  return exact ? encode64_exact_fix<L>(x, y, z, w) : w;
 }
 
 // precision dispatch
-template <class L, int MODE, int PREC>
+template <class L, int MODE, int PREC, int TDEG = 15>
 VC_DI uint64_t encode_vec(float x, float y, float z, const Params& P)
 {
-  if constexpr (PREC == PREC_F64) return encode_vec64<L, MODE>(x, y, z, P);
+  if constexpr (PREC == PREC_F64) return encode_vec64<L, MODE, TDEG>(x, y, z, P);
   else return encode_vec32<L, MODE>(x, y, z, P);
 }
 

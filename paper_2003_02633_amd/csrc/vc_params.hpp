@@ -6,6 +6,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "../../include/vc.h"
 #include "../../include/vc_device.hpp"
 
@@ -157,6 +159,57 @@ static inline double fit_tanh_ratio64(double gamma, double* w, int deg)
   return maxerr;
 }
 
+// The tanh map's polynomial fits depend on gamma alone and take milliseconds of host time, while
+// resolve() runs on every library call: they are cached per gamma (a small table under a lock;
+// past 16 distinct values the oldest entry is replaced).
+static inline vc_status tanh_fits(float gamma, Params& P)
+{
+  struct Entry {
+    uint32_t gamma_bits;
+    vc_status st;
+    float w[8];
+    int wdeg64;
+    double w64[16];
+  };
+  static std::mutex mu;
+  static Entry table[16];
+  static int used = 0, next = 0;
+  uint32_t gb;
+  memcpy(&gb, &gamma, sizeof gb);
+  std::lock_guard<std::mutex> lk(mu);
+  for (int i = 0; i < used; i++) {
+    if (table[i].gamma_bits == gb) {
+      memcpy(P.w, table[i].w, sizeof P.w);
+      P.wdeg = 7;
+      P.wdeg64 = table[i].wdeg64;
+      memcpy(P.w64, table[i].w64, sizeof P.w64);
+      return table[i].st;
+    }
+  }
+  Entry e;
+  memset(&e, 0, sizeof e);
+  e.gamma_bits = gb;
+  e.st = VC_SUCCESS;
+  const double err = fit_tanh_tail((double)gamma, e.w, 7);
+  if (err > 2e-8) e.st = VC_ERROR_UNSUPPORTED_CODEC;   // residual relative to |Q| scales like the 1-ulp window
+  // smallest degree whose double-precision fit is within 1e-14 (the level error near the
+  // phi poles is Kc times this residual)
+  double err64 = 1.0;
+  for (e.wdeg64 = 6; e.wdeg64 <= 15; e.wdeg64++) {
+    memset(e.w64, 0, sizeof e.w64);
+    err64 = fit_tanh_ratio64((double)gamma, e.w64, e.wdeg64);
+    if (err64 <= 1e-14) break;
+  }
+  if (err64 > 1e-14) e.st = VC_ERROR_UNSUPPORTED_CODEC;
+  Entry& slot = used < 16 ? table[used++] : table[next++ % 16];
+  slot = e;
+  memcpy(P.w, e.w, sizeof P.w);
+  P.wdeg = 7;
+  P.wdeg64 = e.wdeg64;
+  memcpy(P.w64, e.w64, sizeof P.w64);
+  return e.st;
+}
+
 inline vc_status resolve(const vc_codec* c, Resolved* R)
 {
   if (!c || !R) return VC_ERROR_INVALID_VALUE;
@@ -225,17 +278,8 @@ inline vc_status resolve(const vc_codec* c, Resolved* R)
     P.gam = c->gamma;
     P.inv_gam = 1.0f / c->gamma;
     P.cgam = (float)tanh((double)c->gamma);
-    P.wdeg = 7;
-    const double err = fit_tanh_tail((double)c->gamma, P.w, P.wdeg);
-    if (err > 2e-8) return VC_ERROR_UNSUPPORTED_CODEC;   // residual relative to |Q| scales like the 1-ulp window
-    // smallest degree whose double-precision fit is within 1e-14 (the level error near the
-    // phi poles is Kc times this residual)
-    double err64 = 1.0;
-    for (P.wdeg64 = 6; P.wdeg64 <= 15; P.wdeg64++) {
-      err64 = fit_tanh_ratio64((double)c->gamma, P.w64, P.wdeg64);
-      if (err64 <= 1e-14) break;
-    }
-    if (err64 > 1e-14) return VC_ERROR_UNSUPPORTED_CODEC;
+    const vc_status fst = tanh_fits(c->gamma, P);
+    if (fst != VC_SUCCESS) return fst;
   }
   return VC_SUCCESS;
 }

@@ -35,11 +35,12 @@ __device__ __forceinline__ void st(T* p, T v)
 // in step u lane l handles the pair at w*U*128 + u*128 + 2l, so every load/store instruction of
 // a wave covers 1 KiB contiguous, and the steps of a lane are 1 KiB apart (immediate offsets of
 // one scalar base plus one per-lane byte offset).
-template <class L, int MODE, int PREC, int BS, int U, bool NT, bool DUMP>
+template <class L, int MODE, int PREC, int BS, int U, bool NT, bool DUMP, int TDEG = 15>
 __global__ __launch_bounds__(BS) void k_axpy(const uint64_t* __restrict__ a, const uint64_t* __restrict__ b,
                                              uint64_t* __restrict__ c, size_t n, uint32_t ntiles, float alpha,
-                                             Params P, float* __restrict__ dump)
+                                             Params P0, float* __restrict__ dump)
 {
+  with_compand_mask<MODE>(P0, [&](const Params& P) {
   // tiles [0, ntiles) take the 16-byte path (pointers 16-byte aligned); the rest is scalar
   constexpr size_t TILE = (size_t)2 * BS * U;
   const uint32_t first = (threadIdx.x >> 6) * (U * 128u) + 2u * (threadIdx.x & 63u);   // code index in a tile
@@ -70,7 +71,7 @@ __global__ __launch_bounds__(BS) void k_axpy(const uint64_t* __restrict__ a, con
           const size_t i = t0 + first + (size_t)u * 128 + h;
           dump[3 * i] = cx; dump[3 * i + 1] = cy; dump[3 * i + 2] = cz;
         }
-        out[h] = encode_vec<L, MODE, PREC>(cx, cy, cz, P);
+        out[h] = encode_vec<L, MODE, PREC, TDEG>(cx, cy, cz, P);
       }
       st<NT>(pc + 64 * u, out);
     }
@@ -85,17 +86,20 @@ __global__ __launch_bounds__(BS) void k_axpy(const uint64_t* __restrict__ a, con
     const float cy = __builtin_fmaf(alpha, ay, by);
     const float cz = __builtin_fmaf(alpha, az, bz);
     if constexpr (DUMP) { dump[3 * i] = cx; dump[3 * i + 1] = cy; dump[3 * i + 2] = cz; }
-    c[i] = encode_vec<L, MODE, PREC>(cx, cy, cz, P);
+    c[i] = encode_vec<L, MODE, PREC, TDEG>(cx, cy, cz, P);
   }
+  });
 }
 
 // ------------------------------------------------------------------ encode / decode
-template <class L, int MODE, int PREC, int BS>
+template <class L, int MODE, int PREC, int BS, int TDEG = 15>
 __global__ __launch_bounds__(BS) void k_encode1(const float* __restrict__ xyz, uint64_t* __restrict__ codes,
-                                                size_t n, Params P)
+                                                size_t n, Params P0)
 {
+  with_compand_mask<MODE>(P0, [&](const Params& P) {
   for (size_t i = (size_t)blockIdx.x * BS + threadIdx.x; i < n; i += (size_t)gridDim.x * BS)
-    codes[i] = encode_vec<L, MODE, PREC>(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], P);
+    codes[i] = encode_vec<L, MODE, PREC, TDEG>(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], P);
+  });
 }
 
 // Encode and decode in wave tiles of 256 vectors, so that every load and store instruction of a
@@ -106,8 +110,9 @@ __global__ __launch_bounds__(BS) void k_encode1(const float* __restrict__ xyz, u
 // done one vector per lane.
 template <class L, int MODE, int BS, bool NT>
 __global__ __launch_bounds__(BS) void k_decode_w(const uint64_t* __restrict__ codes, float* __restrict__ xyz,
-                                                 size_t n, Params P)
+                                                 size_t n, Params P0)
 {
+  with_compand_mask<MODE>(P0, [&](const Params& P) {
   __shared__ float stage[BS / 64][256 * 3];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   float* sw = stage[wv];
@@ -134,12 +139,14 @@ __global__ __launch_bounds__(BS) void k_decode_w(const uint64_t* __restrict__ co
   }
   for (size_t i = 256 * ntile + (size_t)blockIdx.x * BS + threadIdx.x; i < n; i += (size_t)gridDim.x * BS)
     decode_vec<L, MODE>(codes[i], P, xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2]);
+  });
 }
 
-template <class L, int MODE, int PREC, int BS, bool NT>
+template <class L, int MODE, int PREC, int BS, bool NT, int TDEG = 15>
 __global__ __launch_bounds__(BS) void k_encode_w(const float* __restrict__ xyz, uint64_t* __restrict__ codes,
-                                                 size_t n, Params P)
+                                                 size_t n, Params P0)
 {
+  with_compand_mask<MODE>(P0, [&](const Params& P) {
   __shared__ float stage[BS / 64][256 * 3];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   float* sw = stage[wv];
@@ -161,24 +168,27 @@ __global__ __launch_bounds__(BS) void k_encode_w(const float* __restrict__ xyz, 
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     u64x2 o0, o1;
-    o0[0] = encode_vec<L, MODE, PREC>(v[0], v[1], v[2], P);
-    o0[1] = encode_vec<L, MODE, PREC>(v[3], v[4], v[5], P);
-    o1[0] = encode_vec<L, MODE, PREC>(v[6], v[7], v[8], P);
-    o1[1] = encode_vec<L, MODE, PREC>(v[9], v[10], v[11], P);
+    o0[0] = encode_vec<L, MODE, PREC, TDEG>(v[0], v[1], v[2], P);
+    o0[1] = encode_vec<L, MODE, PREC, TDEG>(v[3], v[4], v[5], P);
+    o1[0] = encode_vec<L, MODE, PREC, TDEG>(v[6], v[7], v[8], P);
+    o1[1] = encode_vec<L, MODE, PREC, TDEG>(v[9], v[10], v[11], P);
     u64x2* dst = (u64x2*)(codes + 256 * t);
     st<NT>(dst + lane, o0);
     st<NT>(dst + 64 + lane, o1);
   }
   for (size_t i = 256 * ntile + (size_t)blockIdx.x * BS + threadIdx.x; i < n; i += (size_t)gridDim.x * BS)
-    codes[i] = encode_vec<L, MODE, PREC>(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], P);
+    codes[i] = encode_vec<L, MODE, PREC, TDEG>(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], P);
+  });
 }
 
 template <class L, int MODE, int BS>
 __global__ __launch_bounds__(BS) void k_decode1(const uint64_t* __restrict__ codes, float* __restrict__ xyz,
-                                                size_t n, Params P)
+                                                size_t n, Params P0)
 {
+  with_compand_mask<MODE>(P0, [&](const Params& P) {
   for (size_t i = (size_t)blockIdx.x * BS + threadIdx.x; i < n; i += (size_t)gridDim.x * BS)
     decode_vec<L, MODE>(codes[i], P, xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2]);
+  });
 }
 
 // ------------------------------------------------------------------ reductions
@@ -279,12 +289,23 @@ static vc_status axpy_launch(const Resolved& R, float alpha, const uint64_t* a, 
   // would take the rest
   const size_t ntiles = aligned ? (n / TILE < 0x80000000u ? n / TILE : 0x80000000u) : 0;
   const unsigned grid = grid_for(n, TILE, 1u << 30);
-  if (dump)
-    hipLaunchKernelGGL((k_axpy<L, MODE, PREC, BS, U, false, true>), dim3(grid), dim3(BS), 0, s, a, b, c, n,
-                       (uint32_t)ntiles, alpha, R.P, dump);
-  else
-    hipLaunchKernelGGL((k_axpy<L, MODE, PREC, BS, U, NT, false>), dim3(grid), dim3(BS), 0, s, a, b, c, n,
-                       (uint32_t)ntiles, alpha, R.P, dump);
+  // the tanh map's encoder evaluates the polynomial degree the fit needs (two instantiations)
+  const bool low = MODE == TANH && PREC == PREC_F64 && tanh_tdeg(R.P.wdeg64) == 8;
+  if (dump) {
+    if (low)
+      hipLaunchKernelGGL((k_axpy<L, MODE, PREC, BS, U, false, true, 8>), dim3(grid), dim3(BS), 0, s, a, b, c, n,
+                         (uint32_t)ntiles, alpha, R.P, dump);
+    else
+      hipLaunchKernelGGL((k_axpy<L, MODE, PREC, BS, U, false, true>), dim3(grid), dim3(BS), 0, s, a, b, c, n,
+                         (uint32_t)ntiles, alpha, R.P, dump);
+  } else {
+    if (low)
+      hipLaunchKernelGGL((k_axpy<L, MODE, PREC, BS, U, NT, false, 8>), dim3(grid), dim3(BS), 0, s, a, b, c, n,
+                         (uint32_t)ntiles, alpha, R.P, dump);
+    else
+      hipLaunchKernelGGL((k_axpy<L, MODE, PREC, BS, U, NT, false>), dim3(grid), dim3(BS), 0, s, a, b, c, n,
+                         (uint32_t)ntiles, alpha, R.P, dump);
+  }
   return launch_status();
 }
 
@@ -319,19 +340,27 @@ static vc_status axpy_t(const Resolved& R, float alpha, const uint64_t* a, const
   }
 }
 
-template <class L, int MODE, int PREC>
-static vc_status encode_t(const Resolved& R, const float* xyz, uint64_t* codes, size_t n, hipStream_t s)
+template <class L, int MODE, int PREC, int TDEG>
+static vc_status encode_d(const Resolved& R, const float* xyz, uint64_t* codes, size_t n, hipStream_t s)
 {
   constexpr int BS = 256;
   const bool aligned = (((uintptr_t)xyz | (uintptr_t)codes) & 15u) == 0;
   if (aligned) {
     const unsigned grid = grid_for(n, (size_t)4 * BS, 1u << 30);
-    hipLaunchKernelGGL((k_encode_w<L, MODE, PREC, BS, true>), dim3(grid), dim3(BS), 0, s, xyz, codes, n, R.P);
+    hipLaunchKernelGGL((k_encode_w<L, MODE, PREC, BS, true, TDEG>), dim3(grid), dim3(BS), 0, s, xyz, codes, n, R.P);
   } else {
     const unsigned grid = grid_for(n, (size_t)BS, 1u << 30);
-    hipLaunchKernelGGL((k_encode1<L, MODE, PREC, BS>), dim3(grid), dim3(BS), 0, s, xyz, codes, n, R.P);
+    hipLaunchKernelGGL((k_encode1<L, MODE, PREC, BS, TDEG>), dim3(grid), dim3(BS), 0, s, xyz, codes, n, R.P);
   }
   return launch_status();
+}
+
+template <class L, int MODE, int PREC>
+static vc_status encode_t(const Resolved& R, const float* xyz, uint64_t* codes, size_t n, hipStream_t s)
+{
+  if (MODE == TANH && PREC == PREC_F64 && tanh_tdeg(R.P.wdeg64) == 8)
+    return encode_d<L, MODE, PREC, 8>(R, xyz, codes, n, s);
+  return encode_d<L, MODE, PREC, 15>(R, xyz, codes, n, s);
 }
 
 template <class L, int MODE, int PREC>

@@ -11,17 +11,29 @@
 
 using namespace vc;
 
-template <class L, int MODE>
-static void enc(const Params& P, int prec, const float* xyz, uint64_t* out, size_t n)
+// as the kernels do: the body under with_compand_mask (compile-time mask and tanh degree when
+// both angles are companded)
+template <class L, int MODE, int TD>
+static void enc_d(const Params& P0, int prec, const float* xyz, uint64_t* out, size_t n)
 {
-  for (size_t i = 0; i < n; i++)
-    out[i] = prec == PREC_F64 ? encode_vec<L, MODE, PREC_F64>(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], P)
-                              : encode_vec<L, MODE, PREC_F32>(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], P);
+  with_compand_mask<MODE>(P0, [&](const Params& P) {
+    for (size_t i = 0; i < n; i++)
+      out[i] = prec == PREC_F64 ? encode_vec<L, MODE, PREC_F64, TD>(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], P)
+                                : encode_vec<L, MODE, PREC_F32, TD>(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], P);
+  });
 }
 template <class L, int MODE>
-static void dec(const Params& P, const uint64_t* w, float* out, size_t n)
+static void enc(const Params& P0, int prec, const float* xyz, uint64_t* out, size_t n)
 {
-  for (size_t i = 0; i < n; i++) decode_vec<L, MODE>(w[i], P, out[3 * i], out[3 * i + 1], out[3 * i + 2]);
+  if (MODE == TANH && tanh_tdeg(P0.wdeg64) == 8) enc_d<L, MODE, 8>(P0, prec, xyz, out, n);
+  else enc_d<L, MODE, 15>(P0, prec, xyz, out, n);
+}
+template <class L, int MODE>
+static void dec(const Params& P0, const uint64_t* w, float* out, size_t n)
+{
+  with_compand_mask<MODE>(P0, [&](const Params& P) {
+    for (size_t i = 0; i < n; i++) decode_vec<L, MODE>(w[i], P, out[3 * i], out[3 * i + 1], out[3 * i + 2]);
+  });
 }
 
 template <class L, int MODE>

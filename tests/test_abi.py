@@ -209,6 +209,28 @@ def test_inline_params(lib):
     assert (nt, npm) == ((1 << 18) - 1, (1 << 17) - 1)
 
 
+def test_tanh_fits_cached_per_gamma(lib):
+    """the tanh map's polynomial fits (milliseconds each) are cached per gamma: interleaved codecs
+    of several gammas get the same constants as when first resolved, and resolving is cheap"""
+    import time
+    size = lib.vcx_inline_params_size()
+
+    def params(g):
+        buf = C.create_string_buffer(size)
+        assert lib.vcx_inline_params(C.byref(vc.codec(mode="tanh", gamma=g)), buf, size) == 0
+        return buf.raw
+    gammas = [0.5, 1.0, 0.25, 0.8125]
+    first = {g: params(g) for g in gammas}
+    assert len(set(first.values())) == len(gammas)
+    for _ in range(3):
+        for g in reversed(gammas):
+            assert params(g) == first[g]
+    t0 = time.perf_counter()
+    for _ in range(2000):
+        params(1.0)
+    assert time.perf_counter() - t0 < 1.0
+
+
 def test_error_hist_validation_without_device_work(lib):
     P = C.byref(vc.codec())
     f = _fake

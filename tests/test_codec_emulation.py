@@ -38,6 +38,9 @@ for _prec in ("f64", "f32"):
         pytest.param("0,7,22-17-18", "tanh", {"gamma": 1.0, "precision": _prec}, marks=_m),
         pytest.param("0,7,22-17-18", "cos", {"precision": _prec}, marks=_m),
     ]
+    # companding of one angle only
+    VARIANTS += [pytest.param("0,7,22-17-18", m, dict(kw, precision=_prec, compand=a), marks=_m)
+                 for m, kw in (("tanh", {"gamma": 0.5}), ("cos", {})) for a in ("phi", "theta")]
     # the paper-literal truncating magnitude (§2.3); only the 22-bit mantissa drops a bit
     VARIANTS += [
         ("0,7,22-17-18", "plain", {"precision": _prec, "mag_round": "trunc"}),

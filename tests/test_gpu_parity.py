@@ -87,6 +87,10 @@ for _prec in ("f64", "f32"):
 VARIANTS += [("0,7,22-17-18", "tanh", {"gamma": 0.5, "precision": "f64"}),
              ("0,7,22-17-18", "tanh", {"gamma": 1.0, "precision": "f64"}),
              ("0,7,22-17-18", "cos", {"precision": "f64"})]
+# companding of one angle only (the kernels' run-time mask path; both angles is compiled apart)
+COMPAND_ONE = [("0,7,22-17-18", m, dict(kw, precision="f64", compand=a))
+               for m, kw in (("tanh", {"gamma": 0.5}), ("cos", {})) for a in ("phi", "theta")]
+VARIANTS += COMPAND_ONE
 # the paper-literal truncating magnitude (§2.3): float32 norm, trailing mantissa bit dropped
 VARIANTS += [("0,7,22-17-18", "plain", {"precision": p, "mag_round": "trunc"}) for p in ("f64", "f32")]
 VARIANTS += [("0,7,22-17-18", "frac", {"P": 163840, "precision": "f32", "mag_round": "trunc"}),
@@ -176,7 +180,25 @@ def _axpy_operands(n, seed_a, seed_b):
     return xa, xb
 
 
-def _check_axpy(torch, c, co, wa, wb, alpha, label, mag_err=2.0 ** -23):
+def _level_stretch(mode, n_max, gamma=0.5):
+    """largest quantisation error of a companded angle (normalised u in [-1, 1]) over the uniform
+    half step 1/n_max.  §2.5: the levels are uniform in h = 2 n/n_max - 1 and decode to
+    u = atanh(tanh(gamma) h)/gamma (tanh) or (2/pi) asin(h) (cosine); rounding is to the nearest
+    level in h, so a value decodes to its level from anywhere up to the midpoints in h on either
+    side, which lie farther than half a step in u where the map is flat (the cosine map's ends)."""
+    h = 2.0 * np.arange(n_max + 1, dtype=np.float64) / n_max - 1.0
+    hm = 0.5 * (h[1:] + h[:-1])
+
+    def u_of(x):
+        if mode == "tanh":
+            return np.arctanh(np.tanh(gamma) * x) / gamma
+        return (2.0 / np.pi) * np.arcsin(np.clip(x, -1.0, 1.0))
+    u, um = u_of(h), u_of(hm)
+    worst = max((um - u[:-1]).max(), (u[1:] - um).max())
+    return float(worst / (1.0 / n_max))
+
+
+def _check_axpy(torch, c, co, wa, wb, alpha, label, mag_err=2.0 ** -23, stretch=(1.0, 1.0)):
     ta, tb = up(torch, wa), up(torch, wb)
     out = vc.vc_axpy(c, alpha, ta, tb)
     out2, c32 = vc.vcx_axpy_dump(c, alpha, ta, tb)
@@ -197,7 +219,7 @@ def _check_axpy(torch, c, co, wa, wb, alpha, label, mag_err=2.0 ** -23):
     scale = alpha * np.linalg.norm(A64, axis=1) + np.linalg.norm(B64, axis=1)
     ok = (nrm > 2.0 ** -70) & (nrm < 1e14)
     nt, npm = O.nmax(co)
-    codec_bound = math.hypot(math.pi / nt, math.pi / (2 * npm)) + mag_err
+    codec_bound = math.hypot(math.pi / nt * stretch[0], math.pi / (2 * npm) * stretch[1]) + mag_err
     err = np.linalg.norm(got - c64, axis=1)[ok]
     allowed = codec_bound * nrm[ok] + (4 * 2.0 ** -24 + 1e-6) * scale[ok]
     say(f"{label}: max end-to-end err/allowed = {(err / allowed).max():.3f}")
@@ -221,6 +243,23 @@ def test_axpy_config1(torch_dev, prec):
     wa, wb = O.encode(co, xa), O.encode(co, xb)
     _check_axpy(torch_dev, c, co, wa, wb, 1.0, "axpy config1 alpha=1")
     _check_axpy(torch_dev, c, co, wa, wb, ALPHA, "axpy config1 alpha=0.7")
+
+
+@pytest.mark.parametrize("mode,kw", [("tanh", {"gamma": 0.5}), ("tanh", {"gamma": 1.0}), ("cos", {}),
+                                     ("tanh", {"gamma": 0.5, "compand": "phi"}),
+                                     ("cos", {"compand": "theta"})])
+def test_axpy_companded(torch_dev, mode, kw):
+    """the companded codecs' axpy (both angles, and one angle only) under the layered contract"""
+    say(f"case: axpy {mode} {kw}")
+    c, co = vc.codec(mode=mode, **kw), O.codec(mode=mode, **kw)
+    xa, xb = _axpy_operands(65536, 4, 5)
+    wa, wb = O.encode(co, xa), O.encode(co, xb)
+    nt, npm = O.nmax(co)
+    mask = kw.get("compand", "both")
+    g = kw.get("gamma", 0.5)
+    st = _level_stretch(mode, nt, g) if mask in ("both", "theta") else 1.0
+    sp = _level_stretch(mode, npm, g) if mask in ("both", "phi") else 1.0
+    _check_axpy(torch_dev, c, co, wa, wb, ALPHA, f"axpy {mode} {kw}", stretch=(st, sp))
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
