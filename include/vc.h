@@ -200,9 +200,10 @@ typedef struct {
 typedef struct vc_batch_plan vc_batch_plan;
 
 /* Build a plan for `nseg` segments (host array, copied; 0 <= nseg <= 2^20).  Each segment is
- * cut into tiles of 512 vectors; one persistent kernel walks all tiles of all segments with a
- * static grid stride, and a second kernel sums the per-tile partials of each dot/norm2
- * segment in a fixed order (deterministic; an empty reduction segment yields 0).  Both are
+ * cut into tiles (512 to 4096 vectors, by operation and the tuned tile shape); one persistent
+ * kernel walks all tiles of all segments with a static grid stride, and a second kernel sums
+ * the per-wave partials of each dot/norm2 segment in a fixed order (deterministic; an empty
+ * reduction segment yields 0).  Both are
  * captured into a HIP graph.  Segments run concurrently, so no segment may write memory that
  * another segment reads or writes (VC_ERROR_OVERLAP); within a segment the rules of the
  * single-call entry points hold (axpy may run in place).  Pointer and size checks as for

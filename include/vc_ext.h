@@ -56,6 +56,13 @@ vc_status vcx_load_tuning(const char* path);
  * into a second HIP graph on first use and replayed: the launch-overhead baseline between
  * plain separate launches and the persistent kernel. */
 vc_status vcx_batch_plan_run_separate_graph(vc_batch_plan* plan, hipStream_t stream);
+/* Tile shape of batch plans created from now on for the default codec (other codecs use
+ * (2, 4, 8)), in code pairs per lane of a 256-thread workgroup: axpy tiles of 512 ua vectors
+ * (ua 1 or 2), dot 512 ud (2, 4 or 8), norm2 512 un (4, 8 or 16); encode tiles are 1024 vectors.
+ * Process-wide, chosen by the autotuner (a tuning-cache line "batch ua=A ud=D un=N" applies it);
+ * other values return VC_ERROR_UNSUPPORTED_CODEC and change nothing. */
+vc_status vcx_set_batch_config(int ua, int ud, int un);
+vc_status vcx_get_batch_config(int* ua, int* ud, int* un);
 /* Number of tiles the plan's persistent kernel walks and its grid size (workgroups). */
 vc_status vcx_batch_plan_info(const vc_batch_plan* plan, uint64_t* total_tiles, uint32_t* grid);
 

@@ -74,6 +74,8 @@ _SIGS = {
     "vcx_load_tuning": ([C.c_char_p], C.c_int),
     "vcx_batch_plan_run_separate_graph": ([_vp, _vp], C.c_int),
     "vcx_batch_plan_info": ([_vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint32)], C.c_int),
+    "vcx_set_batch_config": ([C.c_int, C.c_int, C.c_int], C.c_int),
+    "vcx_get_batch_config": ([C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
     "vc_flux_div_tp": ([C.POINTER(vc_codec), _vp, C.c_int, C.c_int, _vp, _vp, C.c_size_t, _vp], C.c_int),
     "vcb_flux_div_tp_f32": ([_vp, C.c_int, C.c_int, _vp, _vp, C.c_size_t, _vp], C.c_int),
     "vc_gather_decode": ([C.POINTER(vc_codec), _vp, C.c_size_t, _vp, C.c_size_t, _vp, _vp], C.c_int),
@@ -338,6 +340,18 @@ def get_stream_config(precision: str = "f64"):
     _check(lib().vcx_get_stream_config(PRECISIONS[precision], C.byref(b), C.byref(v), C.byref(t)),
            "vcx_get_stream_config")
     return b.value, v.value, t.value
+
+
+def set_batch_config(ua: int, ud: int, un: int):
+    """tile shape of batch plans created from now on (default codec): code pairs per lane for
+    axpy (1, 2), dot (2, 4, 8) and norm2 (4, 8, 16) tiles"""
+    _check(lib().vcx_set_batch_config(ua, ud, un), "vcx_set_batch_config")
+
+
+def get_batch_config():
+    a, d, n = C.c_int(), C.c_int(), C.c_int()
+    _check(lib().vcx_get_batch_config(C.byref(a), C.byref(d), C.byref(n)), "vcx_get_batch_config")
+    return a.value, d.value, n.value
 
 
 def _seg_ptr(seg, key):

@@ -171,6 +171,8 @@ vc_status vcx_load_tuning(const char* path)
       st = p == -2 ? VC_ERROR_INVALID_VALUE : vcx_set_stream_config(p, b, v, t);
     } else if (sscanf(line, "axpy block=%d vpt=%d nt=%d", &b, &v, &t) == 3) {
       st = vcx_set_stream_config(-1, b, v, t);
+    } else if (sscanf(line, "batch ua=%d ud=%d un=%d", &b, &v, &t) == 3) {
+      st = vcx_set_batch_config(b, v, t);
     }
   }
   fclose(f);

@@ -1,10 +1,13 @@
-"""Autotuner for the streaming compressed axpy (block size, vectors per thread, non-temporal).
+"""Autotuner for the streaming compressed axpy (block size, vectors per thread, non-temporal) and
+for the tile shape of the batched persistent kernel (code pairs per lane of axpy, dot and norm2
+tiles).
 
 Sweeps every launch configuration the library is built with on a workload of N vectors
 (default 2^27, the benchmark size), checks that all configurations produce bit-identical
 codes, and writes the fastest one as a tuning cache:
 
     axpy <f64|f32> block=<B> vpt=<V> nt=<T>
+    batch ua=<A> ud=<D> un=<N>
 
 The library applies the file named by $VC_TUNE_CACHE on first use, and
 ``vcx_load_tuning(path)`` applies any cache explicitly.
@@ -73,6 +76,67 @@ def sweep(n: int = 1 << 27, precision: str = "f64", steps: int = 20, settle_ms: 
     return results
 
 
+BATCH_CONFIGS = [(ua, ud, un) for ua in (1, 2) for ud in (2, 4, 8) for un in (4, 8, 16)]
+BATCH_BYTES = {"axpy": 24, "dot": 16, "norm2": 8, "encode": 20}
+
+
+def sweep_batch(precision: str = "f64", steps: int = 20, settle_ms: float = 150.0, log=print):
+    """every tile shape on the 64-segment plan of the benchmark (lengths floor(10^U[3, 7]),
+    seed 3, a shuffled round robin of axpy / dot / norm2 / encode); the axpy and encode codes
+    must be bit-identical across shapes (the reductions' order differs)"""
+    import torch
+
+    import paper_2003_02633_amd as vc
+    from paper_2003_02633_amd import inputs
+
+    c = vc.codec(precision=precision)
+    lengths, ops = inputs.segments(nseg=64, seed=3, lo_exp=3.0, hi_exp=7.0)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(3)
+    segs, algo = [], 0.0
+    for n, op in zip(lengths, ops):
+        n = int(n)
+        x = torch.randn((n, 3), generator=g, dtype=torch.float32, device="cuda")
+        if op == "encode":
+            segs.append({"op": op, "n": n, "a": x, "out": torch.empty(n, dtype=torch.int64, device="cuda")})
+        else:
+            a = vc.vc_encode(c, x)
+            b = vc.vc_encode(c, torch.randn((n, 3), generator=g, dtype=torch.float32, device="cuda")) \
+                if op in ("axpy", "dot") else None
+            out = torch.empty(n, dtype=torch.int64, device="cuda") if op == "axpy" else \
+                torch.empty(1, dtype=torch.float32, device="cuda")
+            segs.append({"op": op, "n": n, "a": a, "b": b, "out": out, "alpha": 0.7})
+        algo += BATCH_BYTES[op] * n
+    saved = vc.get_batch_config()
+    results, ref = [], None
+    try:
+        for cfg in BATCH_CONFIGS:
+            vc.set_batch_config(*cfg)
+            plan = vc.BatchPlan(c, segs)
+            _settle(torch, plan.run, settle_ms)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(steps):
+                plan.run()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            codes = [s["out"][:: max(1, s["n"] // 4096)].clone() for s in segs if s["op"] in ("axpy", "encode")]
+            if ref is None:
+                ref = codes
+            same = all(bool(torch.equal(x, y)) for x, y in zip(codes, ref))
+            plan.close()
+            results.append({"ua": cfg[0], "ud": cfg[1], "un": cfg[2], "ms": ms, "GBs": algo / (ms * 1e-3) / 1e9,
+                            "identical": same})
+            log(f"[tune] batch ua={cfg[0]} ud={cfg[1]} un={cfg[2]}: {ms * 1e3:.1f} us  "
+                f"{algo / (ms * 1e-3) / 1e9:.0f} GB/s  identical={same}")
+    finally:
+        vc.set_batch_config(*saved)
+    if not all(r["identical"] for r in results):
+        raise RuntimeError("batch tile shapes disagree")
+    return results
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--n", type=int, default=1 << 27)
@@ -80,17 +144,23 @@ def main():
     ap.add_argument("--out", default=DEFAULT_CACHE)
     ap.add_argument("--json", default=None, help="also write all timings here")
     args = ap.parse_args()
-    res = sweep(args.n, args.precision, log=lambda m: print(m, file=sys.stderr, flush=True))
+    log = lambda m: print(m, file=sys.stderr, flush=True)
+    res = sweep(args.n, args.precision, log=log)
     best = min(res, key=lambda r: r["ms"])
+    bres = sweep_batch(args.precision, log=log)
+    bbest = min(bres, key=lambda r: r["ms"])
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     with open(args.out, "w") as f:
         f.write(f"# compressed axpy launch configuration, N={args.n}, encoder {args.precision}, "
                 f"{best['gvecs']:.1f} Gvec/s\n")
         f.write(f"axpy {args.precision} block={best['block']} vpt={best['vpt']} nt={best['nt']}\n")
+        f.write(f"# batch tile shape, 64-segment plan, {bbest['GBs']:.0f} GB/s\n")
+        f.write(f"batch ua={bbest['ua']} ud={bbest['ud']} un={bbest['un']}\n")
     if args.json:
         with open(args.json, "w") as f:
-            json.dump({"n": args.n, "precision": args.precision, "results": res, "best": best}, f, indent=1)
-    print(json.dumps({"best": best}), flush=True)
+            json.dump({"n": args.n, "precision": args.precision, "results": res, "best": best,
+                       "batch_results": bres, "batch_best": bbest}, f, indent=1)
+    print(json.dumps({"best": best, "batch_best": bbest}), flush=True)
 
 
 if __name__ == "__main__":

@@ -172,6 +172,7 @@ def test_apply_validation_without_device_work(lib):
 
 def test_tuning_cache_parsing(lib, tmp_path):
     saved = {p: vc.get_stream_config(p) for p in ("f64", "f32")}
+    saved_batch = vc.get_batch_config()
     try:
         f = tmp_path / "tune.txt"
         f.write_text("# comment\naxpy f64 block=256 vpt=2 nt=0\n")
@@ -189,7 +190,16 @@ def test_tuning_cache_parsing(lib, tmp_path):
         assert lib.vcx_set_stream_config(0, 512, 8, 1) == 0       # VC_PREC_F64
         assert vc.get_stream_config("f64") == (512, 8, 1)
         assert lib.vcx_load_tuning(str(tmp_path / "missing").encode()) == 1
+        # the batch tile shape
+        f.write_text("batch ua=1 ud=4 un=8\n")
+        assert lib.vcx_load_tuning(str(f).encode()) == 0
+        assert vc.get_batch_config() == (1, 4, 8)
+        f.write_text("batch ua=3 ud=4 un=8\n")
+        assert lib.vcx_load_tuning(str(f).encode()) == 3
+        assert vc.get_batch_config() == (1, 4, 8)
+        assert lib.vcx_set_batch_config(2, 3, 4) == 3 and lib.vcx_set_batch_config(2, 2, 32) == 3
     finally:
+        vc.set_batch_config(*saved_batch)
         for p, (b, v, t) in saved.items():
             vc.set_stream_config(b, v, t, p)
     assert vc.get_stream_config("f64") == saved["f64"]

@@ -164,14 +164,51 @@ def clobber(torch, segs):
             s["out"].fill_(float("nan"))
 
 
+# edge segments: empty of every op, single vectors, and one vector either side of the tile sizes
+EDGE_LENGTHS = [0, 0, 0, 0, 1, 1, 1, 1, 511, 512, 513, 1023, 1024, 1025, 2047, 2048, 2049, 4095, 4096, 4097,
+                8191, 8192, 8193, 8193]
+EDGE_OPS = ["axpy", "dot", "norm2", "encode"] * 6
+
+
+def expected_tiles(lengths, ops, cfg):
+    """tiles of a plan: 512 ua vectors per axpy tile, 512 ud per dot, 512 un per norm2, 1024 per
+    encode tile"""
+    ua, ud, un = cfg
+    size = {"axpy": 512 * ua, "dot": 512 * ud, "norm2": 512 * un, "encode": 1024}
+    return sum((int(n) + size[op] - 1) // size[op] for n, op in zip(lengths, ops))
+
+
+def test_batch_every_tile_shape(torch_dev):
+    """the mixed segments under every tile shape the autotuner chooses from: codes bit-identical to
+    the single-call entry points (and to the oracle's rule), reductions within the tolerance"""
+    from paper_2003_02633_amd import tune
+    torch = torch_dev
+    lengths, ops = inputs.segments(nseg=24, seed=5, lo_exp=3.0, hi_exp=4.5)
+    lengths, ops = list(lengths) + EDGE_LENGTHS, list(ops) + EDGE_OPS
+    c, co = vc.codec(), O.codec()
+    segs, host = build_segments(torch, co, lengths, ops, pad_every=7)
+    exp = expected_codes(torch, c, segs)
+    saved = vc.get_batch_config()
+    try:
+        for cfg in tune.BATCH_CONFIGS:
+            say(f"case: batch tile shape {cfg}")
+            vc.set_batch_config(*cfg)
+            plan = vc.BatchPlan(c, segs)
+            assert plan.info()[0] == expected_tiles(lengths, ops, cfg)
+            clobber(torch, segs)
+            plan.run()
+            check_results(torch, co, segs, host, exp, f"shape {cfg}", oracle_codes=cfg == tune.BATCH_CONFIGS[0])
+            plan.close()
+    finally:
+        vc.set_batch_config(*saved)
+
+
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 def test_batch_mixed_segments(torch_dev, precision):
     torch = torch_dev
     lengths, ops = inputs.segments(nseg=64, seed=3, lo_exp=3.0, hi_exp=5.0)
     # edge segments: empty of every op, single vectors, one tile +- 1, unaligned operands
-    lengths = list(lengths) + [0, 0, 0, 0, 1, 1, 1, 1, 511, 512, 513, 1025]
-    ops = list(ops) + ["axpy", "dot", "norm2", "encode", "axpy", "dot", "norm2", "encode",
-                       "axpy", "dot", "norm2", "encode"]
+    lengths, ops = list(lengths) + EDGE_LENGTHS, list(ops) + EDGE_OPS
     say(f"case: batch precision={precision} nseg={len(lengths)} total={int(np.sum(lengths))}")
     c, co = vc.codec(precision=precision), O.codec()
     segs, host = build_segments(torch, co, lengths, ops, pad_every=5)
@@ -179,7 +216,7 @@ def test_batch_mixed_segments(torch_dev, precision):
     plan = vc.BatchPlan(c, segs)
     tiles, grid = plan.info()
     say(f"plan: {tiles} tiles, grid {grid}")
-    assert tiles == sum((int(n) + 511) // 512 for n in lengths)
+    assert tiles == expected_tiles(lengths, ops, vc.get_batch_config())
 
     clobber(torch, segs)
     plan.run()
