@@ -201,31 +201,29 @@ def cpu_baseline(torch, wa_dev, wb_dev, target_s: float = 15.0):
                       f"(decode both, single-rounded FMA, encode), OpenMP over {threads} threads, {dt:.1f} s"}
 
 
-def sample_error(torch, wa, wb, wc, nsample: int = 1 << 20, seed: int = 5):
+def sample_error(torch, vc, c, wa, wb, wc, nsample: int = 1 << 20, seed: int = 5):
     """Max normalised error |decode(c) - (alpha a_hat + b_hat)| / |alpha a_hat + b_hat| over a seeded
-    sample (FP64 from the exactly decoded operands, by the oracle)."""
+    sample: the three codes decoded by the library (single precision; its decode error, under
+    3e-7 |x| per component, is a few per cent of the codec's), the sum and the error norms in FP64
+    on the host."""
     import numpy as np
 
-    import oracle as O
-
-    co = O.codec()
     n = wa.numel()
     g = torch.Generator(device="cpu")
     g.manual_seed(seed)
     idx = torch.randint(0, n, (min(nsample, n),), generator=g).to(wa.device)
-    a = wa[idx].cpu().numpy().view(np.uint64)
-    b = wb[idx].cpu().numpy().view(np.uint64)
-    c = wc[idx].cpu().numpy().view(np.uint64)
-    c64 = ALPHA * O.decode64(co, a) + O.decode64(co, b)
-    got = O.decode64(co, c)
+    A = vc.vc_decode(c, wa[idx].contiguous()).double().cpu().numpy()
+    B = vc.vc_decode(c, wb[idx].contiguous()).double().cpu().numpy()
+    got = vc.vc_decode(c, wc[idx].contiguous()).double().cpu().numpy()
+    c64 = float(ALPHA) * A + B
     nrm = np.linalg.norm(c64, axis=1)
-    scale = ALPHA * np.linalg.norm(O.decode64(co, a), axis=1) + np.linalg.norm(O.decode64(co, b), axis=1)
+    scale = float(ALPHA) * np.linalg.norm(A, axis=1) + np.linalg.norm(B, axis=1)
     ok = nrm > 0
     err = np.linalg.norm(got - c64, axis=1)
     return {"max_rel_err": float((err[ok] / nrm[ok]).max()),
             "mean_rel_err": float((err[ok] / nrm[ok]).mean()),
             "max_err_over_operand_scale": float((err[ok] / scale[ok]).max()),
-            "sample": int(idx.numel())}
+            "sample": int(idx.numel()), "decode": "library (single precision)"}
 
 
 def bench_apply(torch, vc, inputs, k: int):
@@ -249,32 +247,81 @@ def bench_apply(torch, vc, inputs, k: int):
             "bound": "mfma", "mfma_floor_us": flop / 157.3e12 * 1e6, "hbm_floor_us": byts / 8e12 * 1e6}
 
 
+ANISO_CODECS = (("plain", {}), ("tanh_g0.5", {"mode": "tanh", "gamma": 0.5}), ("cos", {"mode": "cos"}),
+                ("frac_P2^16", {"mode": "frac", "P": 1 << 16}), ("frac_P163840", {"mode": "frac", "P": 163840}),
+                ("frac_P2^18", {"mode": "frac", "P": 1 << 18}))
+
+
+def _compact_hist(counts):
+    """nonzero span of a histogram: [index of the first nonzero bin, counts up to the last]"""
+    nz = [i for i, v in enumerate(counts) if v]
+    if not nz:
+        return [0, []]
+    return [nz[0], [int(v) for v in counts[nz[0]:nz[-1] + 1]]]
+
+
 def bench_anisotropy(torch, vc, inputs, n: int = 1 << 25):
     """Codec error statistics on the GPU (FP64 error norms) for von Mises-Fisher directions,
-    kappa in {1, 10, 100, 1000}, mean +z and (1,1,1)/sqrt(3), lognormal magnitudes."""
+    kappa in {1, 10, 100, 1000}, mean +z and (1,1,1)/sqrt(3), lognormal magnitudes, for every
+    codec variant: mean / max / rms of the three error measures and the histograms of the angular
+    and magnitude errors (bins 10^(-12 + i/10); bin 0 counts errors below 1e-12)."""
     import numpy as np
 
-    c = vc.codec()
     edges_np = 10.0 ** (-12.0 + np.arange(101, dtype=np.float64) / 10)
     edges = torch.from_numpy(edges_np).to("cuda")
-    res = {"n": n, "edges": "10^(-12 + i/10), i = 0..100"}
+    codecs = [(name, vc.codec(**kw)) for name, kw in ANISO_CODECS]
+    res = {"n": n, "edges": "10^(-12 + i/10), i = 0..100", "kinds": ["|x_hat-x|/|x|", "angle(x, x_hat)", "|r_hat-r|/r"],
+           "hist_format": "[first nonzero bin, counts...] of the angle and magnitude histograms",
+           "codecs": {name: {} for name, _ in codecs}}
     for kappa in (1.0, 10.0, 100.0, 1000.0):
         for mname, mean in (("z", (0.0, 0.0, 1.0)), ("diag", (1.0, 1.0, 1.0))):
             x = inputs.vmf_torch(n, kappa, mean, seed=int(kappa) + (0 if mname == "z" else 7))
             torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            h, ex, st = vc.error_hist(c, x, edges)
-            ms = (time.perf_counter() - t0) * 1e3
-            m = int(h[0].sum())
-            st = st.numpy()
-            rec = {"mean": [float(v) for v in st[:, 0] / m], "max": [float(v) for v in st[:, 2]],
-                   "rms": [float(v) for v in np.sqrt(st[:, 1] / m)], "excluded": ex, "ms": ms}
-            if mname == "z" and kappa in (1.0, 1000.0):
-                rec["hist_angle_nonzero"] = {f"{edges_np[i - 1]:.2e}": int(v) for i, v in
-                                             enumerate(h[1].tolist()) if v and i > 0}
-            res[f"kappa{int(kappa)}_{mname}"] = rec
+            for name, c in codecs:
+                t0 = time.perf_counter()
+                h, ex, st = vc.error_hist(c, x, edges)
+                ms = (time.perf_counter() - t0) * 1e3
+                m = int(h[0].sum())
+                st = st.numpy()
+                res["codecs"][name][f"kappa{int(kappa)}_{mname}"] = {
+                    "mean": [float(v) for v in st[:, 0] / m], "max": [float(v) for v in st[:, 2]],
+                    "rms": [float(v) for v in np.sqrt(st[:, 1] / m)], "excluded": ex, "ms": round(ms, 3),
+                    "hist_angle": _compact_hist(h[1].tolist()), "hist_magnitude": _compact_hist(h[2].tolist())}
             del x
-    res["kinds"] = ["|x_hat-x|/|x|", "angle(x, x_hat)", "|r_hat-r|/r"]
+    return res
+
+
+def storage_error(torch, vc, c_codec, a32, b32, wc, outs, nsample: int = 1 << 20, seed: int = 6):
+    """Error of each storage format's axpy result against the FP64 axpy of the float32 inputs
+    (alpha a + b), over a seeded sample: normalised vector error |c_hat - c|/|c|, the angle between
+    c_hat and c, and |(|c_hat| - |c|)|/|c|; mean and max, computed in FP64 on the host.  `outs` maps
+    a format to its result (float tensor [N, 3] or [N, 4]); the codec's result is decoded by the
+    library (single precision).  Non-finite results (FP16 overflow) are counted and left out of
+    the statistics."""
+    import numpy as np
+
+    n = a32.shape[0]
+    g = torch.Generator(device="cpu")
+    g.manual_seed(seed)
+    idx = torch.randint(0, n, (min(nsample, n),), generator=g).to(a32.device)
+    a = a32[idx].double().cpu().numpy()
+    b = b32[idx].double().cpu().numpy()
+    c = float(ALPHA) * a + b
+    nrm = np.linalg.norm(c, axis=1)
+    res = {"sample": int(idx.numel()), "truth": "alpha a + b in FP64 from the float32 inputs"}
+    got = {"codec": vc.vc_decode(c_codec, wc[idx].contiguous()).double().cpu().numpy()}
+    for k, t in outs.items():
+        got[k] = t[idx][:, :3].double().cpu().numpy()
+    for k, v in got.items():
+        fin = np.isfinite(v).all(axis=1) & (nrm > 0)
+        e = np.linalg.norm(v - c, axis=1)[fin] / nrm[fin]
+        vn = np.linalg.norm(v[fin], axis=1)
+        cosang = np.clip(np.einsum("ij,ij->i", v[fin], c[fin]) / np.maximum(vn * nrm[fin], 1e-300), -1.0, 1.0)
+        ang = np.arccos(cosang)
+        mag = np.abs(vn - nrm[fin]) / nrm[fin]
+        res[k] = {"vector_mean": float(e.mean()), "vector_max": float(e.max()), "angle_mean": float(ang.mean()),
+                  "angle_max": float(ang.max()), "magnitude_mean": float(mag.mean()), "magnitude_max": float(mag.max()),
+                  "nonfinite_fraction": float(1.0 - fin.mean())}
     return res
 
 
@@ -449,7 +496,7 @@ def main():
     achieved = 24.0 * N / (ms * 1e-3) / 1e9
     log(f"compressed axpy: {ms:.3f} ms/step, {gvecs:.2f} Gvec/s, {achieved:.0f} GB/s")
 
-    err = sample_error(torch, wa, wb, wc)
+    err = sample_error(torch, vc, c, wa, wb, wc)
     log(f"sample error: {err}")
 
     extras = {"host": host_info(torch)}
@@ -462,7 +509,7 @@ def main():
                                "GBs": 36.0 * N / (ms_f32 * 1e-3) / 1e9}
         extras["speedup_vs_fp32"] = ms_f32 / ms
         log(f"fp32 axpy: {ms_f32:.3f} ms -> speedup {ms_f32 / ms:.3f}")
-        del c32
+        stored = {"fp32": c32}
         # bf16 / fp16 storage padded to 4 x 16 bit (8 B/vec, the bytes of a code)
         for kind, dt in (("bf16", torch.bfloat16), ("f16", torch.float16)):
             ha = torch.zeros((N, 4), dtype=dt, device=dev)
@@ -480,7 +527,12 @@ def main():
                 rec["subnormal_fraction"] = small / N
             extras[f"{kind}x4_axpy"] = rec
             log(f"{kind}x4 axpy: {ms_h:.3f} ms")
-            del ha, hb, hc, iv
+            stored[f"{kind}x4"] = hc
+            del ha, hb, iv
+        # storage error of each format's axpy against FP64 (sampled, on the host)
+        extras["storage_error_vs_fp64"] = storage_error(torch, vc, c, a32, b32, wc, stored)
+        log(f"storage error: { {k: v['vector_max'] for k, v in extras['storage_error_vs_fp64'].items() if isinstance(v, dict)} }")
+        del stored, c32
         # attainable bandwidth: copy of 2 x 12 N bytes
         src = a32.view(-1)
         dst = torch.empty_like(src)
@@ -516,7 +568,8 @@ def main():
                          ("frac_P163840", {"mode": "frac", "P": 163840}),
                          ("frac_P2^18", {"mode": "frac", "P": 1 << 18}),
                          ("tanh_g0.5", {"mode": "tanh", "gamma": 0.5}),
-                         ("cos", {"mode": "cos"})):
+                         ("cos", {"mode": "cos"}),
+                         ("trunc_magnitude", {"mag_round": "trunc"})):
             cv = vc.codec(precision=args.precision, **kw)
             va_ = vc.vc_encode(cv, a32)
             vb_ = vc.vc_encode(cv, b32)
@@ -536,8 +589,9 @@ def main():
         log(f"gather: {extras['gather']}")
         log("anisotropy error statistics (vMF, 2^25 vectors each)")
         extras["anisotropy"] = bench_anisotropy(torch, vc, inputs)
-        log(f"anisotropy: " + ", ".join(f"{k}: {v['mean'][0]:.3e}" for k, v in extras["anisotropy"].items()
-                                        if isinstance(v, dict)))
+        log("anisotropy (mean vector error, kappa 1 / 1000 about +z): " + ", ".join(
+            f"{name}: {cases['kappa1_z']['mean'][0]:.3e} / {cases['kappa1000_z']['mean'][0]:.3e}"
+            for name, cases in extras["anisotropy"]["codecs"].items()))
         log("batched segments (64 segments, 10^3..10^7 vectors)")
         extras["batch"] = bench_batch(torch, vc, inputs, k, args.precision)
         log(f"batch: {extras['batch']}")

@@ -91,6 +91,9 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2003_02633_amd.build`")
+        # torch first: its HIP runtime is then the one libvc.so binds to.  Loaded the other way
+        # round, the process holds two HIP runtimes, and the library's finds no device.
+        _torch()
         L = C.CDLL(LIB_PATH)
         for name, (args, res) in _SIGS.items():
             f = getattr(L, name)

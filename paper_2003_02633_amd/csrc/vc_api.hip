@@ -249,7 +249,8 @@ static vc_status reduce_common(const vc_codec* c, const uint64_t* a, const uint6
     if (st != VC_SUCCESS) return st;
     return is_dot ? launch_dot(R, a, b, n, parts, np, d_out, stream) : launch_norm2(R, a, n, parts, np, d_out, stream);
   }
-  if (hipMallocAsync((void**)&parts, sizeof(float) * np, stream) != hipSuccess) return VC_ERROR_OUT_OF_MEMORY;
+  const hipError_t ae = hipMallocAsync((void**)&parts, sizeof(float) * np, stream);
+  if (ae != hipSuccess) return ae == hipErrorOutOfMemory ? VC_ERROR_OUT_OF_MEMORY : VC_ERROR_HIP;
   st = is_dot ? launch_dot(R, a, b, n, parts, np, d_out, stream) : launch_norm2(R, a, n, parts, np, d_out, stream);
   if (hipFreeAsync(parts, stream) != hipSuccess && st == VC_SUCCESS) st = VC_ERROR_HIP;
   return st;

@@ -10,6 +10,9 @@
 // Histograms: bin = number of edges <= e (edges ascending, FP64, staged in LDS, binary search).
 // Each workgroup accumulates LDS counters and FP64 sums; a second kernel (one workgroup per
 // output slot) sums the per-workgroup partials in a fixed order, so the result is deterministic.
+#include <stdio.h>
+#include <stdlib.h>
+
 #include "vc_internal.hpp"
 #include "../../include/vc_ext.h"
 
@@ -216,7 +219,11 @@ extern "C" vc_status vcx_error_hist(const vc_codec* c, const float* xyz, size_t 
   double* ps = nullptr;
   const size_t bytes = (size_t)(groups ? groups : 1) * ((size_t)nc * sizeof(uint32_t) + 9 * sizeof(double));
   void* scratch = nullptr;
-  if (hipMallocAsync(&scratch, bytes, stream) != hipSuccess) return VC_ERROR_OUT_OF_MEMORY;
+  const hipError_t ae = hipMallocAsync(&scratch, bytes, stream);
+  if (ae != hipSuccess) {
+    if (getenv("VC_LOG")) fprintf(stderr, "[vc] vcx_error_hist: hipMallocAsync(%zu) failed: %s\n", bytes, hipGetErrorString(ae));
+    return ae == hipErrorOutOfMemory ? VC_ERROR_OUT_OF_MEMORY : VC_ERROR_HIP;
+  }
   ps = (double*)scratch;
   pc = (uint32_t*)((char*)scratch + (size_t)(groups ? groups : 1) * 9 * sizeof(double));
   st = launch_errhist(R, xyz, n, edges, nedges, pc, ps, groups, stream);

@@ -44,7 +44,11 @@ def stats(vc, c, kind: str, n: int, seed: int, radius: float = 1.0, chunk: int =
     for i, s in enumerate(range(0, n, chunk)):
         k = min(chunk, n - s)
         x = inputs.sampler_torch(kind, k, seed * 1000 + i, radius=radius)
-        h, ex, st = vc.error_hist(c, x, _edges(torch))
+        try:
+            h, ex, st = vc.error_hist(c, x, _edges(torch))
+        except vc.VcError as e:
+            raise RuntimeError(f"{kind} chunk {i} ({k} vectors): {e}; "
+                               f"torch reserved {torch.cuda.memory_reserved() / 2**30:.1f} GiB") from e
         cnt = int(h[0].sum())
         s1 += float(st[0, 0])
         s2 += float(st[0, 1])
