@@ -411,7 +411,12 @@ inline constexpr int tanh_tdeg(int fitted) { return fitted <= 8 ? 8 : 15; }
 // (grid never finer than 2^-149 when keep_sub), by integer arithmetic on the
 // float bit patterns.  Returns the integer significand j and grid exponent g
 // with r_hat = j 2^g (j == 0 for the zero vector).
-VC_NOINL void exact_norm_round(float x, float y, float z, int prec, bool keep_sub, uint32_t& j_out, int& g_out)
+struct NormRound {
+  uint32_t j;   // significand (j == 0 for the zero vector)
+  int g;        // grid exponent: r_hat = j 2^g
+};
+// (returned by value, in registers: the call of this rare path needs no stack frame)
+VC_NOINL NormRound exact_norm_round(float x, float y, float z, int prec, bool keep_sub)
 {
   uint32_t Mf[3], Ef[3];
   const float c[3] = {x, y, z};
@@ -424,7 +429,7 @@ VC_NOINL void exact_norm_round(float x, float y, float z, int prec, bool keep_su
     Ef[i] = e;
     if (m && (int)e > Emax) Emax = (int)e;
   }
-  if (Emax < 0) { j_out = 0; g_out = 0; return; }
+  if (Emax < 0) return NormRound{0u, 0};
   // S in units of 2^(2 Emax - 300 - 64): term_i = Mf^2 << (2 (Ef - Emax) + 64)
   unsigned __int128 S = 0;
   bool sticky = false;
@@ -475,8 +480,7 @@ VC_NOINL void exact_norm_round(float x, float y, float z, int prec, bool keep_su
   if (T4 > m2 || (T4 == m2 && sticky)) j += 1;
   else if (T4 == m2 && (j & 1)) j += 1;           // exact tie: to even
   if (j >> prec) { j >>= 1; g += 1; }             // carried into the next binade
-  j_out = (uint32_t)j;
-  g_out = g;
+  return NormRound{(uint32_t)j, g};
 }
 
 // Angle of (num, den), num, den >= 0 given as double-floats, as a level
@@ -646,7 +650,9 @@ VC_DI uint64_t encode_vec32(float x, float y, float z, const Params& P)
   if (amb) {
     uint32_t j;
     int g;
-    exact_norm_round(x, y, z, L::mr + 1, L::keep_sub, j, g);
+    const NormRound nr = exact_norm_round(x, y, z, L::mr + 1, L::keep_sub);
+    j = nr.j;
+    g = nr.g;
     if constexpr (L::trunc) { j >>= L::mr - L::m; g += L::mr - L::m; }
     if (j >= (1u << L::m)) {                      // normal
       e_r = g + L::m;
@@ -894,7 +900,9 @@ VC_DI uint64_t encode64_exact_fix(float x, float y, float z, uint64_t w)
   uint32_t j;
   int g, e_r;
   uint32_t Mfield;
-  exact_norm_round(x, y, z, L::mr + 1, L::keep_sub, j, g);
+  const NormRound nr = exact_norm_round(x, y, z, L::mr + 1, L::keep_sub);
+  j = nr.j;
+  g = nr.g;
   if constexpr (L::trunc) { j >>= L::mr - L::m; g += L::mr - L::m; }
   if (j >= (1u << L::m)) { e_r = g + L::m; Mfield = j - (1u << L::m); }
   else { e_r = -L::bias; Mfield = j; }

@@ -104,7 +104,9 @@ int emu_dot_pair(const vc_codec* c, const uint64_t* a, const uint64_t* b, float*
 
 int emu_exact_norm(float x, float y, float z, int prec, int keep_sub, uint32_t* j, int* g)
 {
-  exact_norm_round(x, y, z, prec, keep_sub != 0, *j, *g);
+  const NormRound nr = exact_norm_round(x, y, z, prec, keep_sub != 0);
+  *j = nr.j;
+  *g = nr.g;
   return 0;
 }
 
