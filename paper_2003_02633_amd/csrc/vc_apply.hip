@@ -17,8 +17,11 @@
 //     up to 24 mod 32 words, so the four quarters hit different banks); rows beyond `rows` are
 //     read clamped and never stored;
 //   * the results leave through LDS: a lane's accumulators are 4 rows of one element, which
-//     written directly make 64 scattered 12-byte pieces per store; staged per 16-row block, each
-//     element's rows are contiguous and consecutive lanes store consecutive 8-byte pairs.
+//     written directly make 64 scattered 12-byte pieces per store.  Where LDS has room (WHOLE),
+//     each wave stages 4 complete elements at a time, the image of 4 x rows x 3 contiguous floats
+//     of `out`, and writes it with 16-byte stores, every store instruction 1 KiB contiguous;
+//     otherwise it stages one 16-row block of its 16 elements at a time and consecutive lanes
+//     store consecutive 8-byte pairs of each element's 192-byte run.
 // A workgroup is 8 waves (128 elements per step) sharing one copy of M, one workgroup per CU,
 // persistent over the element tiles (the last, partial round spread over the CUs).
 #include "vc_internal.hpp"
@@ -29,6 +32,8 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int APPLY_WAVES = 8;
 constexpr int APPLY_EPW = 16;      // elements per wave
+constexpr int APPLY_AHEAD = 4;     // K-steps whose codes are in flight ahead of their use
+constexpr int APPLY_MTC = 2;       // row blocks per unit of work in the last, partial round
 
 // A load the optimiser keeps where it is written (a relaxed wavefront-scope atomic load is an
 // ordinary global load, but it is not sunk to its use, so it stays one K-step ahead)
@@ -40,7 +45,151 @@ __device__ __forceinline__ uint64_t ld_keep(const uint64_t* p)
 // LDS row stride: >= rows and == 24 (mod 32) words
 inline __host__ __device__ int apply_rs(int rows) { return rows + ((24 - rows % 32) + 32) % 32; }
 
-template <class L, int MODE, int MT>
+// floats of per-wave output staging: 4 whole elements, or one 16-row block of 16 elements (the
+// row-block stores of the last tiles use the whole-element area too)
+inline __host__ __device__ int apply_stage(bool whole, int rows)
+{
+  return whole && 12 * rows > 16 * 48 ? 12 * rows : 16 * 48;
+}
+
+// One tile's products: acc[m] = rows 16 (m0 + m) .. 16 (m0 + m) + 15 of M . X over all K, for the
+// 16 elements of the tile (lane: element j, K quarter q).  Rows past `rows` are computed from
+// clamped operator reads and never stored.
+template <class L, int MODE, int NM>
+__device__ __forceinline__ void tile_mma(f32x4 (&acc)[NM][3], const float* As, int RS, int KS, int rows, int cols,
+                                         const uint64_t* __restrict__ Ue, bool e_ok, int j, int q, int m0,
+                                         const Params& P)
+{
+#pragma unroll
+  for (int m = 0; m < NM; m++)
+#pragma unroll
+    for (int c = 0; c < 3; c++) acc[m][c] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  // The codes of the next APPLY_AHEAD steps are in flight while step s multiplies: a ring of
+  // registers, slot d holding the code of the steps d, d + APPLY_AHEAD, ... (loaded from a
+  // clamped, always valid address).  A lane whose operand row is past `cols`, or whose element
+  // is past the end, uses the zero code instead, which decodes to (0, 0, 0).
+  uint64_t ring[APPLY_AHEAD];
+#pragma unroll
+  for (int d = 0; d < APPLY_AHEAD; d++) {
+    const int k = 4 * d + q;
+    ring[d] = ld_keep(Ue + (k < cols ? k : cols - 1));
+  }
+  for (int s0 = 0; s0 < KS; s0 += APPLY_AHEAD) {
+#pragma unroll
+    for (int d = 0; d < APPLY_AHEAD; d++) {
+      const int s = s0 + d;
+      if (s >= KS) break;                       // uniform
+      const int k = 4 * s + q;
+      const uint64_t w = (e_ok && k < cols) ? ring[d] : 0ull;
+      const int kn = k + 4 * APPLY_AHEAD;
+      ring[d] = ld_keep(Ue + (kn < cols ? kn : cols - 1));
+      float bx, by, bz;
+      decode_vec<L, MODE>(w, P, bx, by, bz);
+      const float* Ak = As + k * RS;
+      float a[NM];
+#pragma unroll
+      for (int m = 0; m < NM; m++) {
+        const int r = 16 * (m0 + m) + j;
+        a[m] = Ak[r < rows ? r : rows - 1];
+      }
+#pragma unroll
+      for (int m = 0; m < NM; m++) acc[m][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[m], bx, acc[m][0], 0, 0, 0);
+#pragma unroll
+      for (int m = 0; m < NM; m++) acc[m][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[m], by, acc[m][1], 0, 0, 0);
+#pragma unroll
+      for (int m = 0; m < NM; m++) acc[m][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[m], bz, acc[m][2], 0, 0, 0);
+    }
+  }
+}
+
+__device__ __forceinline__ void wave_lds_sync()
+{
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// D[i][jj] at lane jj + 16 (i/4), register i%4: a lane holds rows 16m + 4q + (0..3) of element j
+// for the three components.
+//
+// Whole tiles: elements 4g .. 4g+3 (the lanes with j / 4 == g) are staged as their image in
+// `out`, [4][rows][3]; it starts 48 rows g bytes past the tile, so with `out` 16-byte aligned the
+// wave writes it with aligned 16-byte stores, each store instruction 1 KiB contiguous.
+template <int MT>
+__device__ __forceinline__ void store_whole(const f32x4 (&acc)[MT][3], float* st, float* __restrict__ out, int rows,
+                                            size_t t0, size_t n_elem, int lane, int j, int q)
+{
+  const int nf = 12 * rows;                          // floats of 4 elements
+  for (int g = 0; g < 4; g++) {
+    const size_t eg0 = t0 + 4 * g;
+    if (eg0 >= n_elem) break;                        // uniform across the wave
+    if ((j >> 2) == g) {
+      float* se = st + (j & 3) * (3 * rows);
+#pragma unroll
+      for (int m = 0; m < MT; m++)
+#pragma unroll
+        for (int rr = 0; rr < 4; rr++) {
+          const int r = 16 * m + 4 * q + rr;
+          if (m < MT - 1 || r < rows)                // rows past the end are not staged
+#pragma unroll
+            for (int c = 0; c < 3; c++) se[3 * r + c] = acc[m][c][rr];
+        }
+    }
+    wave_lds_sync();
+    float* og = out + eg0 * (size_t)rows * 3;
+    if (n_elem - eg0 >= 4) {
+      const float4* s4 = (const float4*)st;
+      float4* o4 = (float4*)og;
+      for (int i = lane; i < nf / 4; i += 64) o4[i] = s4[i];
+    } else {
+      const int nv = (int)(n_elem - eg0) * 3 * rows;
+      for (int i = lane; i < nv; i += 64) og[i] = st[i];
+    }
+    wave_lds_sync();
+  }
+}
+
+// Row blocks m0 .. m0 + NM - 1 (those below `rows`) of the tile's 16 elements: each 16-row block
+// is staged as 16 element blocks of 48 floats and written back with consecutive lanes on
+// consecutive 8-byte pairs (an element's block of rows is contiguous in `out`).
+template <int NM>
+__device__ __forceinline__ void store_blocks(const f32x4 (&acc)[NM][3], float* st, float* __restrict__ out, int rows,
+                                             size_t t0, size_t n_elem, int m0, int pairs, int lane, int j, int q)
+{
+#pragma unroll
+  for (int m = 0; m < NM; m++) {
+    const int mb = m0 + m;
+    if (16 * mb >= rows) break;                      // uniform
+#pragma unroll
+    for (int rr = 0; rr < 4; rr++)
+#pragma unroll
+      for (int c = 0; c < 3; c++) st[j * 48 + (4 * q + rr) * 3 + c] = acc[m][c][rr];
+    wave_lds_sync();
+    const int nr = rows - 16 * mb < 16 ? rows - 16 * mb : 16;   // rows of this block (>= 1)
+    if (nr == 16 && pairs) {
+#pragma unroll
+      for (int i = 0; i < 6; i++) {
+        const int f2 = i * 64 + lane;               // pair index over 16 elements x 24 pairs
+        const int el = f2 / 24, off = 2 * (f2 - el * 24);
+        const size_t eg = t0 + el;
+        if (eg < n_elem) {
+          const float2 v = *(const float2*)(st + el * 48 + off);
+          *(float2*)(out + eg * (size_t)rows * 3 + 48 * mb + off) = v;
+        }
+      }
+    } else {
+      const int nb = 3 * nr;
+      for (int f = lane; f < 16 * nb; f += 64) {
+        const int el = f / nb, off = f - el * nb;
+        const size_t eg = t0 + el;
+        if (eg < n_elem) out[eg * (size_t)rows * 3 + 48 * mb + off] = st[el * 48 + off];
+      }
+    }
+    wave_lds_sync();
+  }
+}
+
+template <class L, int MODE, int MT, bool WHOLE>
 __global__ __launch_bounds__(64 * APPLY_WAVES) void k_apply(const float* __restrict__ M, int rows, int cols,
                                                               int KS, int RS, const uint64_t* __restrict__ U,
                                                               float* __restrict__ out, size_t n_elem, int pairs,
@@ -58,92 +207,49 @@ __global__ __launch_bounds__(64 * APPLY_WAVES) void k_apply(const float* __restr
   const int wave = threadIdx.x >> 6;
   const int j = lane & 15;        // column within a tile = element within the wave's 16
   const int q = lane >> 4;        // K quarter
+  float* st = As + KP * RS + wave * apply_stage(WHOLE, rows);
   // Tiles: R full rounds in which wave w of workgroup b takes tile i W + 8 b + w (W waves in
-  // all), then the rem = ntiles mod W left over go one per wave in the order (w, b) = (0, 0),
-  // (0, 1), ...: waves 0-3 of every workgroup before any wave 4-7, so the last round spreads
-  // over as many CUs and SIMDs as it can instead of filling a few CUs with 8 waves each.
+  // all).  The rem = ntiles mod W tiles left over are cut into units of APPLY_MTC row blocks
+  // when that gives no wave more than one unit (else a unit is a whole tile), and the units go
+  // one per wave in the order (w, b) = (0, 0), (0, 1), ...: waves 0-3 of every workgroup before
+  // any wave 4-7, so the last round spreads over as many CUs and SIMDs as it can.
   const size_t ntiles = (n_elem + APPLY_EPW - 1) / APPLY_EPW;
   const size_t W = (size_t)gridDim.x * APPLY_WAVES;
   const size_t R = ntiles / W, rem = ntiles - R * W;
   const size_t kx = (size_t)wave * gridDim.x + blockIdx.x;     // this wave's rank in the last round
-  const size_t mine = R + (kx < rem ? 1 : 0);
-  for (size_t i = 0; i < mine; i++) {
-    const size_t t = i < R ? i * W + (size_t)blockIdx.x * APPLY_WAVES + wave : R * W + kx;
+  for (size_t i = 0; i < R; i++) {
+    const size_t t = i * W + (size_t)blockIdx.x * APPLY_WAVES + wave;
+    const size_t e = t * APPLY_EPW + j;      // past the end only in the last tile (rem == 0)
+    const bool e_ok = e < n_elem;
+    f32x4 acc[MT][3];
+    tile_mma<L, MODE, MT>(acc, As, RS, KS, rows, cols, U + (e_ok ? e : 0) * (size_t)cols, e_ok, j, q, 0, P);
+    if constexpr (WHOLE)
+      store_whole<MT>(acc, st, out, rows, t * APPLY_EPW, n_elem, lane, j, q);
+    else
+      store_blocks<MT>(acc, st, out, rows, t * APPLY_EPW, n_elem, 0, pairs, lane, j, q);
+  }
+  constexpr int MTC = MT < APPLY_MTC ? MT : APPLY_MTC;
+  constexpr int NC = (MT + MTC - 1) / MTC;
+  if (NC > 1 && rem * NC <= W) {
+    for (size_t u = kx; u < rem * NC; u += W) {
+      const size_t t = R * W + u / NC;
+      const int m0 = (int)(u % NC) * MTC;
+      const size_t e = t * APPLY_EPW + j;
+      const bool e_ok = e < n_elem;
+      f32x4 acc[MTC][3];
+      tile_mma<L, MODE, MTC>(acc, As, RS, KS, rows, cols, U + (e_ok ? e : 0) * (size_t)cols, e_ok, j, q, m0, P);
+      store_blocks<MTC>(acc, st, out, rows, t * APPLY_EPW, n_elem, m0, pairs, lane, j, q);
+    }
+  } else if (kx < rem) {
+    const size_t t = R * W + kx;
     const size_t e = t * APPLY_EPW + j;
     const bool e_ok = e < n_elem;
-    const uint64_t* Ue = U + (e_ok ? e : 0) * (size_t)cols;
     f32x4 acc[MT][3];
-#pragma unroll
-    for (int m = 0; m < MT; m++)
-#pragma unroll
-      for (int c = 0; c < 3; c++) acc[m][c] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-
-    // the code of step s + 1 is loaded while step s multiplies (from a clamped, always valid
-    // address; its validity is applied where it is used)
-    int kn = q;
-    uint64_t wraw = ld_keep(Ue + (kn < cols ? kn : cols - 1));
-    bool wok = e_ok && kn < cols;
-    for (int s = 0; s < KS; s++) {
-      const int k = kn;
-      const uint64_t w = wok ? wraw : 0ull;      // the zero code decodes to (0, 0, 0)
-      kn += 4;
-      wraw = ld_keep(Ue + (kn < cols ? kn : cols - 1));
-      wok = e_ok && kn < cols;
-      float bx, by, bz;
-      decode_vec<L, MODE>(w, P, bx, by, bz);
-      const float* Ak = As + k * RS;
-      float a[MT];
-#pragma unroll
-      for (int m = 0; m < MT; m++) {
-        const int r = 16 * m + j;                 // rows past the end are read clamped, never stored
-        a[m] = Ak[r < rows ? r : rows - 1];
-      }
-#pragma unroll
-      for (int m = 0; m < MT; m++) acc[m][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[m], bx, acc[m][0], 0, 0, 0);
-#pragma unroll
-      for (int m = 0; m < MT; m++) acc[m][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[m], by, acc[m][1], 0, 0, 0);
-#pragma unroll
-      for (int m = 0; m < MT; m++) acc[m][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[m], bz, acc[m][2], 0, 0, 0);
-    }
-    // D[i][jj] at lane jj + 16 (i/4), register i%4: this lane holds rows 16m + 4q + (0..3) of
-    // element e, for the three components.  Each 16-row block is staged through this wave's LDS
-    // area as 16 element blocks of 48 floats and written back with consecutive lanes on
-    // consecutive 8-byte pairs (an element's block of rows is contiguous in `out`).
-    float* st = As + KP * RS + wave * (16 * 48);
-    const size_t t0 = t * APPLY_EPW;
-#pragma unroll
-    for (int m = 0; m < MT; m++) {
-#pragma unroll
-      for (int rr = 0; rr < 4; rr++)
-#pragma unroll
-        for (int c = 0; c < 3; c++) st[j * 48 + (4 * q + rr) * 3 + c] = acc[m][c][rr];
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      const int nr = rows - 16 * m < 16 ? rows - 16 * m : 16;   // rows of this block (>= 1)
-      if (nr == 16 && pairs) {
-#pragma unroll
-        for (int i = 0; i < 6; i++) {
-          const int f2 = i * 64 + lane;             // pair index over 16 elements x 24 pairs
-          const int el = f2 / 24, off = 2 * (f2 - el * 24);
-          const size_t eg = t0 + el;
-          if (eg < n_elem) {
-            const float2 v = *(const float2*)(st + el * 48 + off);
-            *(float2*)(out + eg * (size_t)rows * 3 + 48 * m + off) = v;
-          }
-        }
-      } else {
-        const int nb = 3 * nr;
-        for (int f = lane; f < 16 * nb; f += 64) {
-          const int el = f / nb, off = f - el * nb;
-          const size_t eg = t0 + el;
-          if (eg < n_elem) out[eg * (size_t)rows * 3 + 48 * m + off] = st[el * 48 + off];
-        }
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
+    tile_mma<L, MODE, MT>(acc, As, RS, KS, rows, cols, U + (e_ok ? e : 0) * (size_t)cols, e_ok, j, q, 0, P);
+    if constexpr (WHOLE)
+      store_whole<MT>(acc, st, out, rows, t * APPLY_EPW, n_elem, lane, j, q);
+    else
+      store_blocks<MT>(acc, st, out, rows, t * APPLY_EPW, n_elem, 0, pairs, lane, j, q);
   }
 }
 
@@ -153,25 +259,38 @@ static vc_status apply_mt(const Resolved& R, const float* M, int rows, int cols,
 {
   const int KS = (cols + 3) / 4;
   const int RS = apply_rs(rows);
-  const size_t lds = ((size_t)4 * KS * RS + (size_t)APPLY_WAVES * 16 * 48) * sizeof(float);
   int dev = 0, ncu = 256;
+  size_t lds_max = 64 * 1024;
   if (hipGetDevice(&dev) == hipSuccess) {
     hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+      ncu = prop.multiProcessorCount;
+      // the opt-in limit (160 KiB on gfx950); the default per-block limit is 64 KiB
+      lds_max = prop.sharedMemPerBlockOptin > prop.sharedMemPerBlock ? prop.sharedMemPerBlockOptin
+                                                                     : prop.sharedMemPerBlock;
+    }
   }
+  // whole-element staging where it fits beside M and `out` is 16-byte aligned
+  const size_t lds_m = (size_t)4 * KS * RS * sizeof(float);
+  const size_t lds_whole = lds_m + (size_t)APPLY_WAVES * apply_stage(true, rows) * sizeof(float);
+  const bool whole = lds_whole <= lds_max && ((uintptr_t)out & 15u) == 0;
+  const size_t lds = whole ? lds_whole : lds_m + (size_t)APPLY_WAVES * apply_stage(false, rows) * sizeof(float);
   const size_t ntiles = (n_elem + APPLY_EPW - 1) / APPLY_EPW;
   size_t grid = (ntiles + APPLY_WAVES - 1) / APPLY_WAVES;
   const size_t cap = (size_t)ncu;                   // one resident workgroup per CU
   if (grid > cap) grid = cap;
   if (grid < 1) grid = 1;
-  if (lds > 64 * 1024 &&
-      hipFuncSetAttribute((const void*)k_apply<L, MODE, MT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
-          hipSuccess)
+  const void* fn = whole ? (const void*)k_apply<L, MODE, MT, true> : (const void*)k_apply<L, MODE, MT, false>;
+  if (lds > 64 * 1024 && hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return VC_ERROR_HIP;
   // 8-byte stores need an even row length (3 rows) and an 8-byte aligned output
   const int pairs = (rows % 2 == 0) && (((uintptr_t)out & 7u) == 0);
-  hipLaunchKernelGGL((k_apply<L, MODE, MT>), dim3((unsigned)grid), dim3(64 * APPLY_WAVES), lds, s, M, rows, cols,
-                     KS, RS, U, out, n_elem, pairs, R.P);
+  if (whole)
+    hipLaunchKernelGGL((k_apply<L, MODE, MT, true>), dim3((unsigned)grid), dim3(64 * APPLY_WAVES), lds, s, M, rows,
+                       cols, KS, RS, U, out, n_elem, pairs, R.P);
+  else
+    hipLaunchKernelGGL((k_apply<L, MODE, MT, false>), dim3((unsigned)grid), dim3(64 * APPLY_WAVES), lds, s, M, rows,
+                       cols, KS, RS, U, out, n_elem, pairs, R.P);
   return launch_status();
 }
 

@@ -28,10 +28,16 @@ def torch_dev():
     return torch
 
 
-def _run(torch, c, M, U):
+def _run(torch, c, M, U, offset=0):
+    """offset > 0 places the output `offset` floats into a buffer (a 4-byte aligned output)"""
     tM = torch.from_numpy(np.ascontiguousarray(M)).to("cuda")
     tU = torch.from_numpy(np.ascontiguousarray(U).view(np.int64)).to("cuda")
-    out = vc.vc_fused_apply(c, tM, tU)
+    out = None
+    if offset:
+        n = U.shape[0] * M.shape[0] * 3
+        out = torch.full((n + offset,), float("nan"), dtype=torch.float32, device="cuda")[offset:]
+        out = out.view(U.shape[0], M.shape[0], 3)
+    out = vc.vc_fused_apply(c, tM, tU, out)
     torch.cuda.synchronize()
     return out.cpu().numpy()
 
@@ -50,13 +56,36 @@ def _check(co, M, U, got, label):
                                               (32, 8, 64), (47, 125, 100), (256, 20, 40), (150, 125, 1),
                                               # 2,054 tiles on 256 workgroups of 8 waves: one full round
                                               # and 6 tiles spread over the workgroups' first waves
-                                              (16, 4, 16 * 2054 - 13)])
+                                              (16, 4, 16 * 2054 - 13),
+                                              # M (76 KB) and 8 waves' whole-element staging (98 KB)
+                                              # exceed the LDS: the 16-row block staging runs
+                                              (256, 68, 41),
+                                              # on 256 workgroups (2,048 waves): 2,048 tiles, the last
+                                              # one partial, all in the full round
+                                              (32, 8, 16 * 2048 - 5),
+                                              # one full round and 100 tiles left over, cut into 5
+                                              # units of 2 row blocks each
+                                              (150, 8, 16 * 2148 - 3),
+                                              # 500 tiles left over: 5 units each would give some
+                                              # waves two, so they stay whole
+                                              (150, 8, 16 * 2548 - 7)])
 def test_apply_shapes(torch_dev, rows, cols, n_elem):
     say(f"case: apply rows={rows} cols={cols} n_elem={n_elem}")
     c, co = vc.codec(), O.codec()
     M = inputs.uniform_matrix(rows, cols, 2)
     U = O.encode(co, inputs.gaussian(n_elem * cols, 7)).reshape(n_elem, cols)
     _check(co, M, U, _run(torch_dev, c, M, U), f"apply {rows}x{cols} E={n_elem}")
+
+
+@pytest.mark.parametrize("offset", [1, 2, 4])
+def test_apply_output_alignment(torch_dev, offset):
+    """Outputs 4, 8 and 16 bytes into a buffer: element staging needs 16-byte alignment, the
+    block staging's pair stores 8; the others take the single-float stores."""
+    say(f"case: apply 150x125 E=70 output offset {offset} floats")
+    c, co = vc.codec(), O.codec()
+    M = inputs.uniform_matrix(150, 125, 2)
+    U = O.encode(co, inputs.gaussian(70 * 125, 9)).reshape(70, 125)
+    _check(co, M, U, _run(torch_dev, c, M, U, offset), f"apply offset {offset}")
 
 
 def test_apply_tgv_field(torch_dev):
