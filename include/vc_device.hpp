@@ -101,6 +101,15 @@ VC_DI double fmin64_nn(double a, double b) { return a < b ? a : b; }
 VC_DI double fmax64_nn(double a, double b) { double r; asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b)); return r; }
 VC_DI double fmin64_nn(double a, double b) { double r; asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b)); return r; }
 #endif
+// A level coordinate about to be converted to an integer, from an encoder path whose result is
+// discarded for non-finite input (the slow path of the caller replaces it).  On the GPU the
+// conversion of a NaN or an infinity is a defined instruction (0 or saturation) and the value is
+// never used; the host build, where such a conversion is undefined, clamps it first.
+#ifdef VC_HOST_EMULATION
+VC_DI double level_guard(double q) { return fmin64_nn(q, 0x1p30); }
+#else
+VC_DI double level_guard(double q) { return q; }
+#endif
 VC_DI float fabs_(float x) { return ubits(fbits(x) & 0x7fffffffu); }
 #ifdef VC_HOST_EMULATION
 VC_DI float fmax_(float a, float b) { return fmaxf(a, b); }
@@ -215,12 +224,39 @@ VC_DI float decode_mag(uint64_t w)
   return r;
 }
 
+// The magnitude bits alone, for codes that are neither the zero code nor the reserved code
+// (special_code false): decode_mag without its two selects.
+template <class L>
+VC_DI float decode_mag_fast(uint64_t w)
+{
+  const uint32_t hi = (uint32_t)(w >> 32);
+  const uint32_t em = ubfe_<L::sh_m - 32, L::e + L::m>(hi);
+  return ubits(L::keep_sub ? em << (23 - L::m) : (em << (23 - L::m)) + ((uint32_t)(127 - L::bias) << 23));
+}
+
+// The codes whose magnitude is not (1 + M/2^m) 2^(E - b): the zero code (E = 0, for layouts
+// without subnormal codes) and the reserved code (E all ones).
+template <class L>
+VC_DI bool special_code(uint64_t w)
+{
+  constexpr int es = L::sh_e - 32;
+  const uint32_t hi = (uint32_t)(w >> 32);
+  if constexpr (L::keep_sub) {
+    return (hi & (L::emask << es)) == (L::emask << es);
+  } else {
+    // E is the top field of the word (no sign bit): E - 1 wraps below 1 and reaches emask - 1
+    // at the reserved exponent, whatever the mantissa bits below it
+    static_assert(L::s == 0, "layouts without subnormal codes have no sign bit");
+    return hi - (1u << es) >= ((L::emask - 1u) << es);
+  }
+}
+
 // The fields of a code: magnitude r_hat (NaN for codes past the fractional split's limit) and
 // the level counts n_theta, n_phi (Eq. q_split for the fractional split).
-template <class L, int MODE>
+template <class L, int MODE, bool FAST = false>
 VC_DI void decode_fields(uint64_t w, const Params& P, float& r, uint32_t& nth, uint32_t& nph)
 {
-  r = decode_mag<L>(w);
+  r = FAST ? decode_mag_fast<L>(w) : decode_mag<L>(w);
   if (MODE == FRAC) {
     const uint64_t np = w & ((1ull << (L::p + L::t)) - 1ull);
     if (np >= P.limit) r = ubits(0x7fc00000u);
@@ -326,12 +362,14 @@ VC_DI void cos_map_trig(uint32_t nth, uint32_t nph, const Params& P, float& st, 
 }
 
 // Cartesian vector of a code: Eq. (a_inv) then Eq. (cart2sphere).
-template <class L, int MODE>
+// FAST: for codes with special_code false only (the magnitude without the zero and reserved
+// cases)
+template <class L, int MODE, bool FAST = false>
 VC_DI void decode_vec(uint64_t w, const Params& P, float& ox, float& oy, float& oz)
 {
   float r;
   uint32_t nth, nph;
-  decode_fields<L, MODE>(w, P, r, nth, nph);
+  decode_fields<L, MODE, FAST>(w, P, r, nth, nph);
   float st, ct, sp, cp;
   if constexpr (MODE == COS) {
     cos_map_trig(nth, nph, P, st, ct, sp, cp);
@@ -797,7 +835,7 @@ VC_DI double compand64(double q, double invK, const Params& P)
 // other case, non-finite input, underflow and saturation included, comes out final, by selects,
 // so the only branch of encode_vec64 is the rare exact one.
 template <class L, int MODE, int TDEG = 15>
-VC_DI uint64_t encode_vec64_fast(float x, float y, float z, const Params& P, bool& exact)
+VC_DI uint64_t encode_vec64_fast(float x, float y, float z, const Params& P, bool& slow, bool& bad)
 {
   // |x|, |y|, |z| converted exactly; the squares are exact in FP64.  The signs come from the
   // inputs below.  A NaN in any component reaches r^2 and the non-finite test.
@@ -806,12 +844,11 @@ VC_DI uint64_t encode_vec64_fast(float x, float y, float z, const Params& P, boo
   // r^2, two roundings (2^-52).  A finite float squares to below 2^256, so r^2 is finite exactly
   // when every component is.  The squares of nonzero floats are at least 2^-298, so raising r^2
   // to 2^-1000 changes only the zero vector, whose norm 2^-500 then flushes to the zero code
-  // below like any norm under the smallest magnitude (through the exact path, where the layout
-  // keeps subnormals).  For non-finite input the arithmetic below runs on infinities and NaNs
-  // and its result is replaced by the reserved code at the end; the level conversions clamp
-  // their operand first, so they stay defined.
+  // below like any norm under the smallest magnitude (through the exact path).  For non-finite
+  // input the arithmetic below runs on infinities and NaNs and the caller replaces its result
+  // with the reserved code.
   const double S0 = fma64_(Z, Z, R2);
-  const bool bad = !(S0 < __builtin_huge_val());  // non-finite input (the test is false for NaN)
+  bad = !(S0 < __builtin_huge_val());             // non-finite input (the test is false for NaN)
   const double S = fmax64_nn(S0, 0x1p-1000);
 
   // ---- magnitude: r to ~2^-47 (rsqrt seed + one Newton step), nearest-even at 1+mr bits
@@ -829,13 +866,15 @@ VC_DI uint64_t encode_vec64_fast(float x, float y, float z, const Params& P, boo
   constexpr uint64_t rb_lo = (uint64_t)(1024 - L::bias) << 52;
   constexpr uint64_t rb_hi = (uint64_t)(1024 - L::bias + L::emax) << 52;
   if (L::keep_sub) amb = amb || rb < rb_lo + (1ull << 52);   // E <= 1: subnormal codes, exact path
-  exact = amb && !bad;
-  const bool under = rb < rb_lo;                  // underflow flushes to the zero code
+  // the slow path (the caller's): non-finite input, a norm near a rounding midpoint, and a code
+  // exponent out of [1, emax] (underflow to the zero code, saturation), all decided there from
+  // the exact norm
+  slow = bad || amb || rb < rb_lo || rb >= rb_hi;
   // the FP64 exponent and fraction fields of rb moved to the code's E|M position, with the
-  // exponent re-biased (modulo 2^64 the bits above the field drop out); saturated above the range
+  // exponent re-biased (modulo 2^64 the bits above the field drop out)
   constexpr int k = L::sh_e - 52;
   static_assert(k > 0, "code exponent field above bit 52");
-  const uint64_t em = rb >= rb_hi ? L::saturated : (rb << k) - ((uint64_t)(1023 - L::bias) << L::sh_e);
+  const uint64_t em = (rb << k) - ((uint64_t)(1023 - L::bias) << L::sh_e);
 
   // ---- rho = sqrt(x^2 + y^2) to ~2^-47 (R2 + 2^-1000 == R2 unless R2 == 0).  With z = 0 this
   //      is the same computation on the same value as r above, so rho == r exactly there.
@@ -851,7 +890,7 @@ VC_DI uint64_t encode_vec64_fast(float x, float y, float z, const Params& P, boo
   const bool yneg = y < 0.0f, xneg = x < 0.0f, zneg = z < 0.0f;
   double Q = half_angle_levels64<true, false>(Y, rho + X, xneg, 0.5 * P.Kt64, 2.0 * P.Ct64);
   if ((MODE == TANH || MODE == COS) && P.comp_t) Q = compand64<MODE, TDEG>(Q, P.invKt64, P);
-  Q = fmin64_nn(Q, 0x1p30);                       // a (quiet) NaN or infinity (non-finite input) -> 2^30
+  Q = level_guard(Q);
   uint32_t nth;
   if (MODE == FRAC) {
     const double Qs = yneg ? -Q : Q;
@@ -870,11 +909,10 @@ VC_DI uint64_t encode_vec64_fast(float x, float y, float z, const Params& P, boo
   if ((MODE == TANH || MODE == COS) && P.comp_p) {
     const double V = half_angle_levels64<false, false>(rho, r + Z, zneg, 0.5 * P.Np64, 2.0 * P.Cp64);
     const double Qc = V - 0.5 * P.Np64;           // (n_phi_max/2) u_phi, exact zero at phi = pi/2
-    const double m = fmin64_nn(compand64<MODE, TDEG>(__builtin_fabs(Qc), P.invKc64, P), 0x1p30);
+    const double m = level_guard(compand64<MODE, TDEG>(__builtin_fabs(Qc), P.invKc64, P));
     nph = (uint32_t)((int)((P.nmax_p + 1u) / 2u) + (int)floor64_(Qc < 0 ? -m : m));
   } else {
-    const double Vh = fmin64_nn(half_angle_levels64<false, true>(rho, r + Z, zneg, 0.5 * P.Np64, 2.0 * P.Cp64),
-                                0x1p30);          // V + 1/2
+    const double Vh = level_guard(half_angle_levels64<false, true>(rho, r + Z, zneg, 0.5 * P.Np64, 2.0 * P.Cp64));   // V + 1/2
     nph = (uint32_t)(int)Vh;                      // Vh >= 0: truncation is the floor
   }
 
@@ -887,13 +925,12 @@ VC_DI uint64_t encode_vec64_fast(float x, float y, float z, const Params& P, boo
     const uint32_t hi = (uint32_t)(em >> 32) | (nph >> (32 - L::t));
     w = ((uint64_t)hi << 32) | lo;
   }
-  w = under && !exact ? 0ull : w;                // (the exact fix needs the angle fields)
-  return bad ? L::reserved : w;
+  return w;
 }
 
 // The code's E and M fields from the exact norm (nearest-even at 1+mr bits, decided by integer
-// arithmetic), merged with the angle fields of `w` (a code of the same vector): the cases
-// encode_vec64_fast leaves to it.  Underflow gives the zero code, overflow saturates.
+// arithmetic), merged with the angle fields of `w` (a code of the same finite vector): the cases
+// encode_vec64_fast leaves to the slow path.  Underflow gives the zero code, overflow saturates.
 template <class L>
 VC_DI uint64_t encode64_exact_fix(float x, float y, float z, uint64_t w)
 {
@@ -917,9 +954,10 @@ VC_DI uint64_t encode64_exact_fix(float x, float y, float z, uint64_t w)
 template <class L, int MODE, int TDEG = 15>
 VC_DI uint64_t encode_vec64(float x, float y, float z, const Params& P)
 {
-  bool exact;
-  const uint64_t w = encode_vec64_fast<L, MODE, TDEG>(x, y, z, P, exact);
-  return exact ? encode64_exact_fix<L>(x, y, z, w) : w;
+  bool slow, bad;
+  const uint64_t w = encode_vec64_fast<L, MODE, TDEG>(x, y, z, P, slow, bad);
+  if (slow) return bad ? L::reserved : encode64_exact_fix<L>(x, y, z, w);
+  return w;
 }
 
 // precision dispatch

@@ -62,8 +62,12 @@ __global__ __launch_bounds__(BS) void k_axpy(const uint64_t* __restrict__ a, con
 #pragma unroll
       for (int h = 0; h < 2; h++) {
         float ax, ay, az, bx, by, bz;
-        decode_vec<L, MODE>(va[u][h], P, ax, ay, az);
-        decode_vec<L, MODE>(vb[u][h], P, bx, by, bz);
+        decode_vec<L, MODE, true>(va[u][h], P, ax, ay, az);
+        decode_vec<L, MODE, true>(vb[u][h], P, bx, by, bz);
+        if (special_code<L>(va[u][h]) || special_code<L>(vb[u][h])) {   // zero or reserved codes (rare)
+          decode_vec<L, MODE>(va[u][h], P, ax, ay, az);
+          decode_vec<L, MODE>(vb[u][h], P, bx, by, bz);
+        }
         const float cx = __builtin_fmaf(alpha, ax, bx);
         const float cy = __builtin_fmaf(alpha, ay, by);
         const float cz = __builtin_fmaf(alpha, az, bz);
