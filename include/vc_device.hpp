@@ -451,13 +451,16 @@ inline constexpr int tanh_tdeg(int fitted) { return fitted <= 8 ? 8 : 15; }
 // with r_hat = j 2^g (j == 0 for the zero vector).
 struct NormRound {
   uint32_t j;   // significand (j == 0 for the zero vector)
-  int g;        // grid exponent: r_hat = j 2^g
+  int g;        // grid exponent: r_hat = j 2^g; NORM_NONFINITE for non-finite input
 };
+constexpr int NORM_NONFINITE = -0x7fffffff;
 // (returned by value, in registers: the call of this rare path needs no stack frame)
 VC_NOINL NormRound exact_norm_round(float x, float y, float z, int prec, bool keep_sub)
 {
   uint32_t Mf[3], Ef[3];
   const float c[3] = {x, y, z};
+  if (umax3(fbits(x) & 0x7fffffffu, fbits(y) & 0x7fffffffu, fbits(z) & 0x7fffffffu) >= 0x7f800000u)
+    return NormRound{0u, NORM_NONFINITE};
   int Emax = -1;
   for (int i = 0; i < 3; i++) {
     uint32_t u = fbits(c[i]) & 0x7fffffffu;
@@ -766,14 +769,15 @@ VC_DI uint64_t encode_vec32(float x, float y, float z, const Params& P)
 // cheaper than the double-float single-precision path.  The hardware FP64
 // reciprocal/rsqrt are ~2^-24 accurate and get one correction step each.
 
-// Level coordinate of an angle a in [0, pi] from the tangent of its half, t = num/den in [0, 1]:
-// a' = 2 atan(t) in [0, pi/2], and a = a' (reflect false) or pi - a' (reflect true).  Kq is the
-// level count of a quarter turn, so a = pi is 2 Kq levels, and C2 = 2 (2 Kq)/pi converts atan to
-// levels.  Above t = tan(pi/8) the ratio is reduced, atan(t) = pi/4 + atan((num - den)/(num + den)),
-// so the polynomial sees |b| <= tan(pi/8).  Returns add + V (reflect false) or add + 2 Kq - V
-// (reflect true), V = [R] Kq + C2 atan(b), with add = 1/2 (HALF) or 0; the offsets are exact.
-// POLE: den may be zero (num = den = 0); it is raised to 2^-1000, so the ratio is 0.
-template <bool POLE, bool HALF>
+// Level coordinate of an angle a in [0, pi] from the tangent of its half, t = num/den in [0, 1]
+// (den > 0): a' = 2 atan(t) in [0, pi/2], and a = a' (reflect false) or pi - a' (reflect true).
+// Kq is the level count of a quarter turn, so a = pi is 2 Kq levels, and C2 = 2 (2 Kq)/pi
+// converts atan to levels.  Above t = tan(pi/8) the ratio is reduced, atan(t) = pi/4 +
+// atan((num - den)/(num + den)), so the polynomial sees |b| <= tan(pi/8).  With V = [R] Kq +
+// C2 atan(b) + add (add = 1/2 for HALF, else 0; the offsets are exact) the result is V, or
+// 2 Kq + 2 add - V when reflected: |f (2 Kq + 2 add) - V| with f = 0 or 1, as V lies in
+// [add, Kq + add].
+template <bool HALF>
 VC_DI double half_angle_levels64(double num, double den, bool reflect, double Kq, double C2)
 {
   constexpr double add = HALF ? 0.5 : 0.0;
@@ -783,8 +787,7 @@ VC_DI double half_angle_levels64(double num, double den, bool reflect, double Kq
   // rounding, or exact when the factor is 0)
   const double Rd = R ? 1.0 : 0.0;
   const double nu = fma64_(-Rd, den, num);
-  double de = fma64_(Rd, num, den);
-  if constexpr (POLE) de = __builtin_fmax(de, 0x1p-1000);
+  const double de = fma64_(Rd, num, den);
   const double rc = rcp64_(de);
   double b = nu * rc;
   b = fma64_(fma64_(-b, de, nu), rc, b);          // quotient to ~2^-48
@@ -793,9 +796,9 @@ VC_DI double half_angle_levels64(double num, double den, bool reflect, double Kq
 #pragma unroll
   for (int i = VC_ATAN_R64_DEG - 1; i >= 0; i--) Rp = fma64_(Rp, s2, VC_ATAN_R64[i]);
   const double at = fma64_(b, s2 * Rp, b);        // atan(b)
-  const double V = fma64_(C2, at, Rd * Kq);
-  if constexpr (HALF) return reflect ? fma64_(2.0, Kq, add) - V : add + V;
-  else return reflect ? 2.0 * Kq - V : V;         // (a -0 from V is harmless: levels are floored)
+  const double V = fma64_(C2, at, fma64_(Rd, Kq, add));
+  const double f = reflect ? 1.0 : 0.0;
+  return __builtin_fabs(fma64_(f, fma64_(2.0, Kq, 2.0 * add), -V));
 }
 
 // Companded level distance from the centre: K h(q/K) for q = K |u| >= 0.
@@ -835,21 +838,21 @@ VC_DI double compand64(double q, double invK, const Params& P)
 // other case, non-finite input, underflow and saturation included, comes out final, by selects,
 // so the only branch of encode_vec64 is the rare exact one.
 template <class L, int MODE, int TDEG = 15>
-VC_DI uint64_t encode_vec64_fast(float x, float y, float z, const Params& P, bool& slow, bool& bad)
+VC_DI uint64_t encode_vec64_fast(float x, float y, float z, const Params& P, bool& slow)
 {
   // |x|, |y|, |z| converted exactly; the squares are exact in FP64.  The signs come from the
   // inputs below.  A NaN in any component reaches r^2 and the non-finite test.
   const double X = (double)__builtin_fabsf(x), Y = (double)__builtin_fabsf(y), Z = (double)__builtin_fabsf(z);
   const double R2 = fma64_(X, X, Y * Y);          // rho^2, one rounding
   // r^2, two roundings (2^-52).  A finite float squares to below 2^256, so r^2 is finite exactly
-  // when every component is.  The squares of nonzero floats are at least 2^-298, so raising r^2
-  // to 2^-1000 changes only the zero vector, whose norm 2^-500 then flushes to the zero code
-  // below like any norm under the smallest magnitude (through the exact path).  For non-finite
-  // input the arithmetic below runs on infinities and NaNs and the caller replaces its result
-  // with the reserved code.
-  const double S0 = fma64_(Z, Z, R2);
-  bad = !(S0 < __builtin_huge_val());             // non-finite input (the test is false for NaN)
-  const double S = fmax64_nn(S0, 0x1p-1000);
+  // when every component is.  The squares of nonzero floats are at least 2^-298, so adding
+  // 2^-1000 to rho^2 changes only rho^2 = 0: r^2 changes only for the zero vector, whose norm
+  // 2^-500 then flushes to the zero code like any norm under the smallest magnitude (through the
+  // exact path).  For non-finite input the arithmetic below runs on infinities and NaNs and the
+  // caller replaces its result with the reserved code.
+  const double R2g = R2 + 0x1p-1000;              // == R2 unless R2 == 0
+  const double S = fma64_(Z, Z, R2g);
+  const bool bad = !(S < __builtin_huge_val());  // non-finite input (the test is false for NaN)
 
   // ---- magnitude: r to ~2^-47 (rsqrt seed + one Newton step), nearest-even at 1+mr bits
   const double yS = rsq64_(S);
@@ -867,8 +870,8 @@ VC_DI uint64_t encode_vec64_fast(float x, float y, float z, const Params& P, boo
   constexpr uint64_t rb_hi = (uint64_t)(1024 - L::bias + L::emax) << 52;
   if (L::keep_sub) amb = amb || rb < rb_lo + (1ull << 52);   // E <= 1: subnormal codes, exact path
   // the slow path (the caller's): non-finite input, a norm near a rounding midpoint, and a code
-  // exponent out of [1, emax] (underflow to the zero code, saturation), all decided there from
-  // the exact norm
+  // exponent out of [1, emax] (underflow to the zero code, saturation), all decided there by the
+  // exact norm
   slow = bad || amb || rb < rb_lo || rb >= rb_hi;
   // the FP64 exponent and fraction fields of rb moved to the code's E|M position, with the
   // exponent re-biased (modulo 2^64 the bits above the field drop out)
@@ -876,19 +879,19 @@ VC_DI uint64_t encode_vec64_fast(float x, float y, float z, const Params& P, boo
   static_assert(k > 0, "code exponent field above bit 52");
   const uint64_t em = (rb << k) - ((uint64_t)(1023 - L::bias) << L::sh_e);
 
-  // ---- rho = sqrt(x^2 + y^2) to ~2^-47 (R2 + 2^-1000 == R2 unless R2 == 0).  With z = 0 this
-  //      is the same computation on the same value as r above, so rho == r exactly there.
-  const double R2g = R2 + 0x1p-1000;
+  // ---- rho = sqrt(x^2 + y^2) to ~2^-47, of R2g: 2^-500 on the z axis, so that the theta ratio
+  //      below is 0 there; otherwise R2g == R2.  With z = 0, R2g == S, so this is the same
+  //      computation on the same value as r above, and rho == r exactly there.
   const double yR = rsq64_(R2g);
-  const double p0 = R2 * yR;
-  const double rho = fma64_(fma64_(-p0, p0, R2), 0.5 * yR, p0);
+  const double p0 = R2g * yR;
+  const double rho = fma64_(fma64_(-p0, p0, R2g), 0.5 * yR, p0);
 
   // ---- theta: |Q| = Kt |theta|/pi; n = base + floor(+-|Q| (+1/2 if n_theta_max is even)).
   //      The half angle of |theta| in [0, pi] has the tangent |y| / (rho + x): from x >= 0,
   //      |y| / (rho + |x|) gives theta' = atan2(|y|, |x|), reflected (pi - theta') for x < 0.
-  //      At the pole (x = y = 0) the ratio is 0/0, made 0: theta = atan2(0, 0) = 0 (R12).
+  //      On the z axis (x = y = 0) rho = 2^-500, so the ratio is 0: theta = atan2(0, 0) = 0 (R12).
   const bool yneg = y < 0.0f, xneg = x < 0.0f, zneg = z < 0.0f;
-  double Q = half_angle_levels64<true, false>(Y, rho + X, xneg, 0.5 * P.Kt64, 2.0 * P.Ct64);
+  double Q = half_angle_levels64<false>(Y, rho + X, xneg, 0.5 * P.Kt64, 2.0 * P.Ct64);
   if ((MODE == TANH || MODE == COS) && P.comp_t) Q = compand64<MODE, TDEG>(Q, P.invKt64, P);
   Q = level_guard(Q);
   uint32_t nth;
@@ -907,12 +910,12 @@ VC_DI uint64_t encode_vec64_fast(float x, float y, float z, const Params& P, boo
   //      At z = 0, rho == r, so the ratio is exactly 1 and phi exactly pi/2 (the tie of R3).
   uint32_t nph;
   if ((MODE == TANH || MODE == COS) && P.comp_p) {
-    const double V = half_angle_levels64<false, false>(rho, r + Z, zneg, 0.5 * P.Np64, 2.0 * P.Cp64);
+    const double V = half_angle_levels64<false>(rho, r + Z, zneg, 0.5 * P.Np64, 2.0 * P.Cp64);
     const double Qc = V - 0.5 * P.Np64;           // (n_phi_max/2) u_phi, exact zero at phi = pi/2
     const double m = level_guard(compand64<MODE, TDEG>(__builtin_fabs(Qc), P.invKc64, P));
     nph = (uint32_t)((int)((P.nmax_p + 1u) / 2u) + (int)floor64_(Qc < 0 ? -m : m));
   } else {
-    const double Vh = level_guard(half_angle_levels64<false, true>(rho, r + Z, zneg, 0.5 * P.Np64, 2.0 * P.Cp64));   // V + 1/2
+    const double Vh = level_guard(half_angle_levels64<true>(rho, r + Z, zneg, 0.5 * P.Np64, 2.0 * P.Cp64));   // V + 1/2
     nph = (uint32_t)(int)Vh;                      // Vh >= 0: truncation is the floor
   }
 
@@ -929,8 +932,9 @@ VC_DI uint64_t encode_vec64_fast(float x, float y, float z, const Params& P, boo
 }
 
 // The code's E and M fields from the exact norm (nearest-even at 1+mr bits, decided by integer
-// arithmetic), merged with the angle fields of `w` (a code of the same finite vector): the cases
-// encode_vec64_fast leaves to the slow path.  Underflow gives the zero code, overflow saturates.
+// arithmetic), merged with the angle fields of `w` (a code of the same vector): the cases
+// encode_vec64_fast leaves to the slow path.  Underflow gives the zero code, overflow saturates,
+// non-finite input gives the reserved code.
 template <class L>
 VC_DI uint64_t encode64_exact_fix(float x, float y, float z, uint64_t w)
 {
@@ -938,6 +942,7 @@ VC_DI uint64_t encode64_exact_fix(float x, float y, float z, uint64_t w)
   int g, e_r;
   uint32_t Mfield;
   const NormRound nr = exact_norm_round(x, y, z, L::mr + 1, L::keep_sub);
+  if (nr.g == NORM_NONFINITE) return L::reserved;
   j = nr.j;
   g = nr.g;
   if constexpr (L::trunc) { j >>= L::mr - L::m; g += L::mr - L::m; }
@@ -954,10 +959,9 @@ VC_DI uint64_t encode64_exact_fix(float x, float y, float z, uint64_t w)
 template <class L, int MODE, int TDEG = 15>
 VC_DI uint64_t encode_vec64(float x, float y, float z, const Params& P)
 {
-  bool slow, bad;
-  const uint64_t w = encode_vec64_fast<L, MODE, TDEG>(x, y, z, P, slow, bad);
-  if (slow) return bad ? L::reserved : encode64_exact_fix<L>(x, y, z, w);
-  return w;
+  bool slow;
+  const uint64_t w = encode_vec64_fast<L, MODE, TDEG>(x, y, z, P, slow);
+  return slow ? encode64_exact_fix<L>(x, y, z, w) : w;
 }
 
 // precision dispatch
