@@ -63,6 +63,16 @@ vc_status vcx_batch_plan_run_separate_graph(vc_batch_plan* plan, hipStream_t str
  * other values return VC_ERROR_UNSUPPORTED_CODEC and change nothing. */
 vc_status vcx_set_batch_config(int ua, int ud, int un);
 vc_status vcx_get_batch_config(int* ua, int* ud, int* un);
+/* Matrix cores of vc_fused_apply, process-wide.  VCX_APPLY_AUTO (the default): the bf16 cores
+ * with every FP32 operand split into three bf16 parts and the six part products that keep
+ * FP32 accuracy (each term within 3 2^-24 |M_ij| |u_j| before FP32 accumulation), where the
+ * operator's three parts fit the LDS beside the output staging (3 rows 32 ceil(cols/32) bf16
+ * plus 24 KiB; M of 150 x 125 does), else the FP32 cores; VCX_APPLY_FP32: always the FP32 cores
+ * (v_mfma_f32_16x16x4f32).  Results agree to FP32 rounding, not bit for bit.  Other values
+ * return VC_ERROR_INVALID_VALUE.  A change may race with launches on other threads. */
+enum { VCX_APPLY_AUTO = 0, VCX_APPLY_FP32 = 1 };
+vc_status vcx_set_apply_mode(int mode);
+int vcx_get_apply_mode(void);
 /* Number of tiles the plan's persistent kernel walks and its grid size (workgroups). */
 vc_status vcx_batch_plan_info(const vc_batch_plan* plan, uint64_t* total_tiles, uint32_t* grid);
 

@@ -76,6 +76,8 @@ _SIGS = {
     "vcx_batch_plan_info": ([_vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint32)], C.c_int),
     "vcx_set_batch_config": ([C.c_int, C.c_int, C.c_int], C.c_int),
     "vcx_get_batch_config": ([C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
+    "vcx_set_apply_mode": ([C.c_int], C.c_int),
+    "vcx_get_apply_mode": ([], C.c_int),
     "vc_flux_div_tp": ([C.POINTER(vc_codec), _vp, C.c_int, C.c_int, _vp, _vp, C.c_size_t, _vp], C.c_int),
     "vcb_flux_div_tp_f32": ([_vp, C.c_int, C.c_int, _vp, _vp, C.c_size_t, _vp], C.c_int),
     "vc_gather_decode": ([C.POINTER(vc_codec), _vp, C.c_size_t, _vp, C.c_size_t, _vp, _vp], C.c_int),
@@ -355,6 +357,20 @@ def get_batch_config():
     a, d, n = C.c_int(), C.c_int(), C.c_int()
     _check(lib().vcx_get_batch_config(C.byref(a), C.byref(d), C.byref(n)), "vcx_get_batch_config")
     return a.value, d.value, n.value
+
+
+APPLY_MODES = {"auto": 0, "fp32": 1}
+
+
+def set_apply_mode(mode: str):
+    """matrix cores of vc_fused_apply: 'auto' (bf16 cores with three-part splits where the
+    operator fits the LDS, else FP32) or 'fp32' (always the FP32 cores)"""
+    _check(lib().vcx_set_apply_mode(APPLY_MODES[mode]), "vcx_set_apply_mode")
+
+
+def get_apply_mode() -> str:
+    m = lib().vcx_get_apply_mode()
+    return {v: k for k, v in APPLY_MODES.items()}[m]
 
 
 def _seg_ptr(seg, key):

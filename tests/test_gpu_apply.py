@@ -28,6 +28,13 @@ def torch_dev():
     return torch
 
 
+@pytest.fixture
+def apply_mode(torch_dev):
+    """sets the apply's matrix cores for one test ('auto': split-bf16 where it fits, 'fp32')"""
+    yield vc.set_apply_mode
+    vc.set_apply_mode("auto")
+
+
 def _run(torch, c, M, U, offset=0):
     """offset > 0 places the output `offset` floats into a buffer (a 4-byte aligned output)"""
     tM = torch.from_numpy(np.ascontiguousarray(M)).to("cuda")
@@ -69,12 +76,14 @@ def _check(co, M, U, got, label):
                                               # 500 tiles left over: 5 units each would give some
                                               # waves two, so they stay whole
                                               (150, 8, 16 * 2548 - 7)])
-def test_apply_shapes(torch_dev, rows, cols, n_elem):
-    say(f"case: apply rows={rows} cols={cols} n_elem={n_elem}")
+@pytest.mark.parametrize("mode", ["auto", "fp32"])
+def test_apply_shapes(torch_dev, apply_mode, rows, cols, n_elem, mode):
+    apply_mode(mode)
+    say(f"case: apply rows={rows} cols={cols} n_elem={n_elem} cores={mode}")
     c, co = vc.codec(), O.codec()
     M = inputs.uniform_matrix(rows, cols, 2)
     U = O.encode(co, inputs.gaussian(n_elem * cols, 7)).reshape(n_elem, cols)
-    _check(co, M, U, _run(torch_dev, c, M, U), f"apply {rows}x{cols} E={n_elem}")
+    _check(co, M, U, _run(torch_dev, c, M, U), f"apply {rows}x{cols} E={n_elem} {mode}")
 
 
 @pytest.mark.parametrize("offset", [1, 2, 4])
@@ -88,9 +97,11 @@ def test_apply_output_alignment(torch_dev, offset):
     _check(co, M, U, _run(torch_dev, c, M, U, offset), f"apply offset {offset}")
 
 
-def test_apply_tgv_field(torch_dev):
+@pytest.mark.parametrize("mode", ["auto", "fp32"])
+def test_apply_tgv_field(torch_dev, apply_mode, mode):
     """The fused-apply workload: TGV velocity at p = 4 solution points (sampled elements)."""
-    say("case: apply tgv 4000 elements")
+    apply_mode(mode)
+    say(f"case: apply tgv 4000 elements cores={mode}")
     c, co = vc.codec(), O.codec()
     M = inputs.uniform_matrix(150, 125, 2)
     vel = inputs.tgv_elements(4000, 4, seed=0)
@@ -105,3 +116,28 @@ def test_apply_rejects_oversize(torch_dev):
     U = torch.zeros((4, 256), dtype=torch.int64, device="cuda")
     with pytest.raises(vc.VcError):
         vc.vc_fused_apply(c, M, U)
+
+
+def test_apply_split_bf16_dynamic_range(torch_dev, apply_mode):
+    """Operator entries and vector magnitudes over many binades (the three bf16 parts of each
+    operand carry its 24 significant bits at any exponent): the bf16 cores still meet the FP32
+    bound, and agree with the FP32 cores to the same bound."""
+    say("case: apply 150x125 E=300 wide dynamic range, both cores")
+    c, co = vc.codec(), O.codec()
+    rng = np.random.default_rng(11)
+    M = (inputs.uniform_matrix(150, 125, 2) * np.exp2(rng.integers(-30, 30, (150, 125)))).astype(np.float32)
+    X = inputs.sphere_loguniform(300 * 125, 12)
+    U = O.encode(co, X).reshape(300, 125)
+    apply_mode("auto")
+    got_bf = _run(torch_dev, c, M, U)
+    _check(co, M, U, got_bf, "apply wide range, bf16 cores")
+    apply_mode("fp32")
+    got_32 = _run(torch_dev, c, M, U)
+    _check(co, M, U, got_32, "apply wide range, FP32 cores")
+
+
+def test_apply_mode_validation(torch_dev):
+    with pytest.raises(vc.VcError):
+        vc.lib()  # (loads the library)
+        vc._check(vc.lib().vcx_set_apply_mode(7), "vcx_set_apply_mode")
+    assert vc.get_apply_mode() == "auto"
