@@ -238,13 +238,26 @@ def bench_apply(torch, vc, inputs, k: int):
     del vel
     M = torch.from_numpy(inputs.uniform_matrix(rows, cols, 2)).to("cuda")
     out = torch.empty((E, rows, 3), dtype=torch.float32, device="cuda")
+    # the default cores (bf16 with three-part splits, FP32-accurate), then the FP32 cores
     ms = timed(torch, lambda: vc.vc_fused_apply(c, M, U.view(E, cols), out), k, WX)
+    vc.set_apply_mode("fp32")
+    try:
+        ms32 = timed(torch, lambda: vc.vc_fused_apply(c, M, U.view(E, cols), out), k, WX)
+    finally:
+        vc.set_apply_mode("auto")
     flop = 2.0 * rows * cols * 3 * E
     byts = 8.0 * cols * E + 12.0 * rows * E
+    # issued matrix work: the operator padded to 16-row blocks and 32-wide K steps, six bf16
+    # part products per FP32 product
+    flop_bf = 6 * 2.0 * (16 * ((rows + 15) // 16)) * (32 * ((cols + 31) // 32)) * 3 * E
     del U, M, out
-    return {"elements": E, "rows": rows, "cols": cols, "ms": ms, "TFLOPs": flop / (ms * 1e-3) / 1e12,
-            "frac_fp32_mfma_peak": flop / (ms * 1e-3) / 157.3e12, "GBs": byts / (ms * 1e-3) / 1e9,
-            "bound": "mfma", "mfma_floor_us": flop / 157.3e12 * 1e6, "hbm_floor_us": byts / 8e12 * 1e6}
+    return {"elements": E, "rows": rows, "cols": cols, "ms": ms, "cores": "bf16, three-part split (FP32 accuracy)",
+            "TFLOPs": flop / (ms * 1e-3) / 1e12, "frac_fp32_mfma_peak": flop / (ms * 1e-3) / 157.3e12,
+            "bf16_issued_TFLOPs": flop_bf / (ms * 1e-3) / 1e12,
+            "frac_bf16_mfma_peak": flop_bf / (ms * 1e-3) / 2.5e15,
+            "GBs": byts / (ms * 1e-3) / 1e9, "bound": "mfma", "bf16_mfma_floor_us": flop_bf / 2.5e15 * 1e6,
+            "fp32_cores": {"ms": ms32, "TFLOPs": flop / (ms32 * 1e-3) / 1e12, "mfma_floor_us": flop / 157.3e12 * 1e6},
+            "hbm_floor_us": byts / 8e12 * 1e6}
 
 
 ANISO_CODECS = (("plain", {}), ("tanh_g0.5", {"mode": "tanh", "gamma": 0.5}), ("cos", {"mode": "cos"}),
