@@ -528,6 +528,8 @@ vc_status launch_apply(const Resolved& R, const float* M, int rows, int cols, co
 {
   switch (R.layout * 4 + R.mode) {
     case 0: return apply_t<L0722, PLAIN>(R, M, rows, cols, U, out, n_elem, s);
+    case 1: return apply_t<L0722, TANH>(R, M, rows, cols, U, out, n_elem, s);
+    case 2: return apply_t<L0722, COS>(R, M, rows, cols, U, out, n_elem, s);
     case 3: return apply_t<L0722, FRAC>(R, M, rows, cols, U, out, n_elem, s);
     case 4: return apply_t<L0723, PLAIN>(R, M, rows, cols, U, out, n_elem, s);
     case 8: return apply_t<L0823, PLAIN>(R, M, rows, cols, U, out, n_elem, s);

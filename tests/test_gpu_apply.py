@@ -141,3 +141,16 @@ def test_apply_mode_validation(torch_dev):
         vc.lib()  # (loads the library)
         vc._check(vc.lib().vcx_set_apply_mode(7), "vcx_set_apply_mode")
     assert vc.get_apply_mode() == "auto"
+
+
+@pytest.mark.parametrize("mode", ["auto", "fp32"])
+@pytest.mark.parametrize("kw", [{"mode": "tanh", "gamma": 0.5}, {"mode": "cos"}, {"mode": "frac", "P": 163840}],
+                         ids=["tanh", "cos", "frac"])
+def test_apply_codec_variants(torch_dev, apply_mode, kw, mode):
+    """The apply decodes with the codec's own inverse maps (companding, fractional split)."""
+    apply_mode(mode)
+    say(f"case: apply 150x125 E=200 codec {kw} cores={mode}")
+    c, co = vc.codec(**kw), O.codec(**kw)
+    M = inputs.uniform_matrix(150, 125, 2)
+    U = O.encode(co, inputs.gaussian(200 * 125, 13)).reshape(200, 125)
+    _check(co, M, U, _run(torch_dev, c, M, U), f"apply {kw} {mode}")
