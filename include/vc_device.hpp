@@ -199,6 +199,12 @@ struct Params {
   double invKt64, invKc64;   // 1/(n_theta_max/2), 1/(n_phi_max/2)
   double invT64;             // fractional split: RN64(1/T) (decode quotient)
   double w64[16];            // tanh: h(u)/u = sum w64[i] (u^2)^i
+  // companding with the single-precision encoder: the level boundaries of the companded
+  // coordinate in the uniform one, T[j] = K h^-1(j / K) as double-float pairs (T[2j], T[2j+1]),
+  // j = 0 .. floor(K) + 1 (T[0] = 0, the last +huge); theta (K = n_theta_max / 2) and phi
+  // (K = n_phi_max / 2).  Device (or, in the host build, host) memory owned by the library.
+  const float* ctab_t;
+  const float* ctab_p;
 };
 
 enum Prec { PREC_F32 = 0, PREC_F64 = 1 };
@@ -643,6 +649,23 @@ VC_DI void compand_levels(float qh, float ql, float K, const Params& P, float& o
 
 // ------------------------------------------------------------------ encode
 
+// The companded level floor(K h(|Q| / K)) from an estimate f0 within one of it: the level is the
+// number of boundaries T[1..] at or below |Q| (double-float qh + ql, not necessarily normalised),
+// and h is increasing, so the signs of |Q| - T[f0] and |Q| - T[f0 + 1] settle it.  Each sign is
+// taken from (qh - Th) + (ql - Tl): the first difference is exact whenever it is small (Sterbenz),
+// so a wrong sign needs |Q| within ~2^-24 |ql| of the boundary; |Q| itself carries the encoder's
+// error (about 2^-44 relative).  Both lie far inside the one-ulp window.
+VC_DI int table_level(int f0, float qh, float ql, const float* T, int jmax)
+{
+  const int f = f0 < 0 ? 0 : (f0 > jmax ? jmax : f0);
+  if (T == nullptr) return f;                       // (every encoding entry point attaches them)
+  const float db = (qh - T[2 * f]) + (ql - T[2 * f + 1]);           // |Q| - (start of level f)
+  if (f > 0 && db < 0.0f) return f - 1;
+  const float dn = (qh - T[2 * f + 2]) + (ql - T[2 * f + 3]);       // |Q| - (start of level f + 1)
+  if (dn >= 0.0f) return f + 1;
+  return f;
+}
+
 // Code of a float32 vector (the compress function of §3), single-precision arithmetic only.
 template <class L, int MODE>
 VC_DI uint64_t encode_vec32(float x, float y, float z, const Params& P)
@@ -718,9 +741,15 @@ VC_DI uint64_t encode_vec32(float x, float y, float z, const Params& P)
   // signs from the unscaled inputs (a tiny component may underflow to -0 when scaled)
   const bool yneg = y < 0.0f, xneg = x < 0.0f, zneg = z < 0.0f;
   angle_levels(fabs_(ys), 0.0f, fabs_(xs), 0.0f, xneg, 0.5f * P.Kt, P.Ct_h, P.Ct_l, qh, ql);
-  if (MODE == TANH || MODE == COS) { if (P.comp_t) compand_levels<MODE>(qh, ql, P.Kt, P, qh, ql); }
   uint32_t nth;
-  if (MODE == FRAC && !P.odd_t) {
+  if ((MODE == TANH || MODE == COS) && P.comp_t) {
+    // the companded level: an estimate from the single-precision map, settled by the table of
+    // boundaries (odd n_theta_max: for y < 0 the level mirrors, base - 1 - f)
+    float mh, ml;
+    compand_levels<MODE>(qh, ql, P.Kt, P, mh, ml);
+    const int f = table_level(floor_dd(mh, ml, 0.0f), qh, ql, P.ctab_t, (int)(P.nmax_t >> 1));
+    nth = yneg ? (uint32_t)((int)P.base_t - 1 - f) : (uint32_t)((int)P.base_t + f);
+  } else if (MODE == FRAC && !P.odd_t) {
     // even n_theta_max: n = n_max/2 + floor(Q + 1/2), Q = +-|Q|
     nth = yneg ? (uint32_t)((int)P.base_t - ceil_dd(qh, ql, -0.5f))
                       : (uint32_t)((int)P.base_t + floor_dd(qh, ql, 0.5f));
@@ -744,10 +773,11 @@ VC_DI uint64_t encode_vec32(float x, float y, float z, const Params& P)
       cl = (sml - (ch - big)) + vl;
     }
     const bool negc = ch < 0.0f || (ch == 0.0f && cl < 0.0f);
-    float mh = negc ? -ch : ch, ml = negc ? -cl : cl;
-    compand_levels<MODE>(mh, ml, Kc, P, mh, ml);
+    const float ah = negc ? -ch : ch, al = negc ? -cl : cl;
+    float mh, ml;
+    compand_levels<MODE>(ah, al, Kc, P, mh, ml);
     const int base_p = (int)((P.nmax_p + 1u) / 2u);
-    const int f = floor_dd(mh, ml, 0.0f);
+    const int f = table_level(floor_dd(mh, ml, 0.0f), ah, al, P.ctab_p, (int)(P.nmax_p >> 1));
     nph = negc ? (uint32_t)(base_p - 1 - f) : (uint32_t)(base_p + f);
     if (z == 0.0f) nph = (uint32_t)base_p;
   } else {

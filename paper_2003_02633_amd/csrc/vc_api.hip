@@ -90,6 +90,7 @@ static vc_status encode_impl(const vc_codec* c, const float* xyz, uint64_t* code
   if (!xyz || !codes) return VC_ERROR_INVALID_VALUE;
   if (!aligned(xyz, 4) || !aligned(codes, 8)) return VC_ERROR_MISALIGNED;
   if (overlaps(xyz, 12 * n, codes, 8 * n)) return VC_ERROR_OVERLAP;
+  if ((st = attach_tables(c, &R)) != VC_SUCCESS) return st;
   return launch_encode(R, xyz, codes, n, stream);
 }
 
@@ -127,6 +128,7 @@ static vc_status axpy_common(const vc_codec* c, float alpha, const uint64_t* a, 
   if ((out != a && overlaps(out, 8 * n, a, 8 * n)) || (out != b && overlaps(out, 8 * n, b, 8 * n)))
     return VC_ERROR_OVERLAP;
   if (dump && !aligned(dump, 4)) return VC_ERROR_MISALIGNED;
+  if ((st = attach_tables(c, &R)) != VC_SUCCESS) return st;
   return launch_axpy(R, alpha, a, b, out, n, dump, stream);
 }
 
@@ -260,8 +262,9 @@ vc_status vcx_inline_params(const vc_codec* c, void* params, size_t size)
 {
   if (!params || size != sizeof(Params)) return VC_ERROR_INVALID_VALUE;
   Resolved R;
-  const vc_status st = resolve(c, &R);
+  vc_status st = resolve(c, &R);
   if (st != VC_SUCCESS) return st;
+  if ((st = attach_tables(c, &R)) != VC_SUCCESS) return st;
   memcpy(params, &R.P, sizeof(Params));
   return VC_SUCCESS;
 }

@@ -463,6 +463,7 @@ vc_status vc_batch_plan_create(vc_batch_plan** plan, const vc_codec* c, const vc
   if (nseg < 0 || nseg > (1 << 20) || (nseg > 0 && !segs)) return VC_ERROR_INVALID_VALUE;
   st = validate(segs, nseg);
   if (st != VC_SUCCESS) return st;
+  if ((st = attach_tables(c, &R)) != VC_SUCCESS) return st;     // axpy and encode segments encode
 
   vc_batch_plan* p = new (std::nothrow) vc_batch_plan;
   if (!p) return VC_ERROR_OUT_OF_MEMORY;

@@ -212,6 +212,7 @@ extern "C" vc_status vcx_error_hist(const vc_codec* c, const float* xyz, size_t 
   if (n && !xyz) return VC_ERROR_INVALID_VALUE;
   if (((uintptr_t)xyz & 3u) || ((uintptr_t)edges & 7u) || ((uintptr_t)counts & 7u) || ((uintptr_t)stats & 7u))
     return VC_ERROR_MISALIGNED;
+  if ((st = attach_tables(c, &R)) != VC_SUCCESS) return st;
   const int nc = 3 * (nedges + 1) + 1;
   size_t g = (n + EH_BS - 1) / EH_BS;
   const int groups = (int)(g > (size_t)EH_GRID ? EH_GRID : g);

@@ -116,6 +116,7 @@ extern "C" vc_status vc_scatter_encode(const vc_codec* c, const float* xyz, cons
   if (!xyz || !idx || (!codes && n_dst)) return VC_ERROR_INVALID_VALUE;
   if (((uintptr_t)codes & 7u) || ((uintptr_t)idx & 3u) || ((uintptr_t)xyz & 3u)) return VC_ERROR_MISALIGNED;
   if (overlap(codes, 8 * n_dst, xyz, 12 * n) || overlap(codes, 8 * n_dst, idx, 4 * n)) return VC_ERROR_OVERLAP;
+  if ((st = attach_tables(c, &R)) != VC_SUCCESS) return st;
   VC_DISPATCH(R, scatter_t, R, xyz, idx, n, codes, n_dst, stream);
 }
 

@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <mutex>
+#include <vector>
 
 #include "../../include/vc.h"
 #include "../../include/vc_device.hpp"
@@ -210,6 +211,88 @@ static inline vc_status tanh_fits(float gamma, Params& P)
   return e.st;
 }
 
+// Level boundaries of a companded angle for the single-precision encoder: T[j] = K h^-1(j / K)
+// in the uniform level coordinate |Q| (j = 1 .. floor(K)), T[0] = 0 and a last entry past every
+// |Q|, each as a double-float pair.  h^-1 is atanh(v tanh g) / g (tanh map, R17) or
+// (2/pi) asin(v) (cosine map, R18), in long double.
+static inline void compand_boundaries(int mode, float gamma, double K, std::vector<float>& T)
+{
+  const int jmax = (int)floor(K);
+  T.assign(2 * (size_t)(jmax + 2), 0.0f);
+  const long double PI = 3.14159265358979323846264338327950288L;
+  const long double g = gamma, tg = tanhl(g);
+  for (int j = 1; j <= jmax; j++) {
+    const long double v = (long double)j / (long double)K;
+    const long double u = mode == VC_MODE_TANH ? atanhl(v * tg) / g : (2.0L / PI) * asinl(v);
+    split_dd((long double)K * u, &T[2 * (size_t)j], &T[2 * (size_t)j + 1]);
+  }
+  T[2 * (size_t)(jmax + 1)] = 3.0e38f;
+  T[2 * (size_t)(jmax + 1) + 1] = 0.0f;
+}
+
+// The boundary tables of (mode, gamma) for theta and phi of the default layout, built once per
+// codec and device and kept until the process ends (up to 16 codecs; the GPU copies are made on
+// the current device).  Only the single-precision encoder of a companded codec uses them.
+static inline vc_status compand_tables(int mode, float gamma, const float** tt, const float** tp)
+{
+  struct Entry {
+    int mode, dev;
+    uint32_t gamma_bits;
+    const float* t;
+    const float* p;
+  };
+  static std::mutex mu;
+  static Entry table[16];
+  static int used = 0;
+  uint32_t gb;
+  memcpy(&gb, &gamma, sizeof gb);
+  if (mode == VC_MODE_COS) gb = 0;                 // the cosine map has no parameter
+  int dev = 0;
+#ifndef VC_HOST_EMULATION
+  if (hipGetDevice(&dev) != hipSuccess) return VC_ERROR_HIP;
+#endif
+  std::lock_guard<std::mutex> lk(mu);
+  for (int i = 0; i < used; i++)
+    if (table[i].mode == mode && table[i].gamma_bits == gb && table[i].dev == dev) {
+      *tt = table[i].t;
+      *tp = table[i].p;
+      return VC_SUCCESS;
+    }
+  if (used == 16) return VC_ERROR_UNSUPPORTED_CODEC;
+  // the default layout's level counts (companding is built for <0,7,22>-17-18 only)
+  std::vector<float> ht, hp;
+  compand_boundaries(mode, gamma, ((1 << 18) - 1) / 2.0, ht);
+  compand_boundaries(mode, gamma, ((1 << 17) - 1) / 2.0, hp);
+  const float *t = nullptr, *p = nullptr;
+#ifdef VC_HOST_EMULATION
+  float* ht_own = new float[ht.size()];
+  float* hp_own = new float[hp.size()];
+  memcpy(ht_own, ht.data(), ht.size() * sizeof(float));
+  memcpy(hp_own, hp.data(), hp.size() * sizeof(float));
+  t = ht_own;
+  p = hp_own;
+#else
+  float *dt = nullptr, *dp = nullptr;
+  if (hipMalloc((void**)&dt, ht.size() * sizeof(float)) != hipSuccess) return VC_ERROR_OUT_OF_MEMORY;
+  if (hipMalloc((void**)&dp, hp.size() * sizeof(float)) != hipSuccess) {
+    (void)hipFree(dt);
+    return VC_ERROR_OUT_OF_MEMORY;
+  }
+  if (hipMemcpy(dt, ht.data(), ht.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(dp, hp.data(), hp.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(dt);
+    (void)hipFree(dp);
+    return VC_ERROR_HIP;
+  }
+  t = dt;
+  p = dp;
+#endif
+  table[used++] = Entry{mode, dev, gb, t, p};
+  *tt = t;
+  *tp = p;
+  return VC_SUCCESS;
+}
+
 inline vc_status resolve(const vc_codec* c, Resolved* R)
 {
   if (!c || !R) return VC_ERROR_INVALID_VALUE;
@@ -219,10 +302,6 @@ inline vc_status resolve(const vc_codec* c, Resolved* R)
   if (c->mag_round > VC_MAG_TRUNC) return VC_ERROR_UNSUPPORTED_CODEC;
   if (c->precision > VC_PREC_F32 || c->reserved0 != 0) return VC_ERROR_INVALID_VALUE;
   if (c->mode != VC_MODE_PLAIN && c->layout != VC_LAYOUT_0_7_22_17_18) return VC_ERROR_UNSUPPORTED_CODEC;
-  // the single-precision encoder's companded level near the phi poles cancels to ~2^-24 of
-  // the level count, far outside the one-ulp window; companding needs the FP64 encoder
-  if (c->precision == VC_PREC_F32 && (c->mode == VC_MODE_TANH || c->mode == VC_MODE_COS))
-    return VC_ERROR_UNSUPPORTED_CODEC;
   memset(R, 0, sizeof(*R));
   R->layout = (int)c->layout;
   R->mode = (int)c->mode;
@@ -281,6 +360,16 @@ inline vc_status resolve(const vc_codec* c, Resolved* R)
     const vc_status fst = tanh_fits(c->gamma, P);
     if (fst != VC_SUCCESS) return fst;
   }
+  return VC_SUCCESS;
+}
+
+// The boundary tables of a resolved codec whose single-precision encoder compands (no-op for
+// every other codec): called by the entry points that encode, after their argument checks, so
+// that validation-only calls (n == 0) and the decode-only paths allocate nothing.
+inline vc_status attach_tables(const vc_codec* c, Resolved* R)
+{
+  if (R->prec == PREC_F32 && (R->mode == VC_MODE_TANH || R->mode == VC_MODE_COS))
+    return compand_tables(R->mode, c->gamma, &R->P.ctab_t, &R->P.ctab_p);
   return VC_SUCCESS;
 }
 

@@ -71,6 +71,7 @@ int emu_encode(const vc_codec* c, const float* xyz, uint64_t* out, size_t n)
   Resolved R;
   vc_status st = resolve(c, &R);
   if (st != VC_SUCCESS) return st;
+  if ((st = attach_tables(c, &R)) != VC_SUCCESS) return st;
   EMU_DISPATCH(R, enc, R.P, R.prec, xyz, out, n);
   return 0;
 }

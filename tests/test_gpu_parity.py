@@ -83,13 +83,15 @@ for _prec in ("f64", "f32"):
                  ("0,7,22-17-18", "0,7,23-17-17", "0,8,23-16-17", "1,8,23-16-16")]
     VARIANTS += [("0,7,22-17-18", "frac", {"P": P, "precision": _prec})
                  for P in (1 << 16, 1 << 17, 163840, 1 << 18)]
-# companding runs with the FP64 encoder only (the library rejects it with the FP32 encoder)
-VARIANTS += [("0,7,22-17-18", "tanh", {"gamma": 0.5, "precision": "f64"}),
-             ("0,7,22-17-18", "tanh", {"gamma": 1.0, "precision": "f64"}),
-             ("0,7,22-17-18", "cos", {"precision": "f64"})]
+# companding with either encoder (the single-precision one settles its levels with the
+# library's boundary tables)
+VARIANTS += [("0,7,22-17-18", "tanh", {"gamma": 0.5, "precision": p}) for p in ("f64", "f32")]
+VARIANTS += [("0,7,22-17-18", "tanh", {"gamma": 1.0, "precision": p}) for p in ("f64", "f32")]
+VARIANTS += [("0,7,22-17-18", "cos", {"precision": p}) for p in ("f64", "f32")]
 # companding of one angle only (the kernels' run-time mask path; both angles is compiled apart)
-COMPAND_ONE = [("0,7,22-17-18", m, dict(kw, precision="f64", compand=a))
-               for m, kw in (("tanh", {"gamma": 0.5}), ("cos", {})) for a in ("phi", "theta")]
+COMPAND_ONE = [("0,7,22-17-18", m, dict(kw, precision=p, compand=a))
+               for m, kw in (("tanh", {"gamma": 0.5}), ("cos", {})) for a in ("phi", "theta")
+               for p in ("f64", "f32")]
 VARIANTS += COMPAND_ONE
 # the paper-literal truncating magnitude (§2.3): float32 norm, trailing mantissa bit dropped
 VARIANTS += [("0,7,22-17-18", "plain", {"precision": p, "mag_round": "trunc"}) for p in ("f64", "f32")]
@@ -245,13 +247,15 @@ def test_axpy_config1(torch_dev, prec):
     _check_axpy(torch_dev, c, co, wa, wb, ALPHA, "axpy config1 alpha=0.7")
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("mode,kw", [("tanh", {"gamma": 0.5}), ("tanh", {"gamma": 1.0}), ("cos", {}),
                                      ("tanh", {"gamma": 0.5, "compand": "phi"}),
                                      ("cos", {"compand": "theta"})])
-def test_axpy_companded(torch_dev, mode, kw):
-    """the companded codecs' axpy (both angles, and one angle only) under the layered contract"""
-    say(f"case: axpy {mode} {kw}")
-    c, co = vc.codec(mode=mode, **kw), O.codec(mode=mode, **kw)
+def test_axpy_companded(torch_dev, mode, kw, prec):
+    """the companded codecs' axpy (both angles, and one angle only) under the layered contract,
+    with either encoder"""
+    say(f"case: axpy {mode} {kw} {prec}")
+    c, co = vc.codec(mode=mode, precision=prec, **kw), O.codec(mode=mode, **kw)
     xa, xb = _axpy_operands(65536, 4, 5)
     wa, wb = O.encode(co, xa), O.encode(co, xb)
     nt, npm = O.nmax(co)

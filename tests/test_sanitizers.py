@@ -42,5 +42,5 @@ def test_device_codec_host_build_clean_under_sanitizers(tmp_path):
            os.path.join(ROOT, "tests", "sanitize", "emu_san_driver.cpp"),
            os.path.join(ROOT, "tests", "hostemu", "vc_hostemu.cpp"), "-o", exe]
     # 4 layouts x 2 roundings x 2 precisions plain, 4 fractional split at each of two level
-    # counts (163840 and the largest accepted, 2^24), 4 companded (FP64 only)
-    assert "codecs run: 28" in _build_and_run(cmd, exe)
+    # counts (163840 and the largest accepted, 2^24), 8 companded (both precisions)
+    assert "codecs run: 32" in _build_and_run(cmd, exe)
