@@ -582,8 +582,12 @@ def main():
                          ("frac_P2^18", {"mode": "frac", "P": 1 << 18}),
                          ("tanh_g0.5", {"mode": "tanh", "gamma": 0.5}),
                          ("cos", {"mode": "cos"}),
-                         ("trunc_magnitude", {"mag_round": "trunc"})):
-            cv = vc.codec(precision=args.precision, **kw)
+                         ("trunc_magnitude", {"mag_round": "trunc"}),
+                         # the single-precision encoder's companding (level-boundary tables)
+                         ("tanh_g0.5_f32encoder", {"mode": "tanh", "gamma": 0.5, "precision": "f32"}),
+                         ("cos_f32encoder", {"mode": "cos", "precision": "f32"})):
+            kw = dict({"precision": args.precision}, **kw)
+            cv = vc.codec(**kw)
             va_ = vc.vc_encode(cv, a32)
             vb_ = vc.vc_encode(cv, b32)
             msv = timed(torch, lambda: vc.vc_axpy(cv, ALPHA, va_, vb_, wc), k, WX)
