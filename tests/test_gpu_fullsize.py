@@ -62,6 +62,8 @@ def _u64(t):
 @pytest.mark.parametrize("label,kw", [("plain-f64", {"precision": "f64"}), ("plain-f32", {"precision": "f32"}),
                                       ("frac163840", {"mode": "frac", "P": 163840}),
                                       ("tanh0.5", {"mode": "tanh", "gamma": 0.5}), ("cos", {"mode": "cos"}),
+                                      ("tanh0.5-f32", {"mode": "tanh", "gamma": 0.5, "precision": "f32"}),
+                                      ("cos-f32", {"mode": "cos", "precision": "f32"}),
                                       ("trunc", {"mag_round": "trunc"}),
                                       ("trunc-f32", {"mag_round": "trunc", "precision": "f32"})])
 def test_axpy_full_size(torch_dev, operands, label, kw):
