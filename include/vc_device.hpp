@@ -651,19 +651,21 @@ VC_DI void compand_levels(float qh, float ql, float K, const Params& P, float& o
 
 // The companded level floor(K h(|Q| / K)) from an estimate f0 within one of it: the level is the
 // number of boundaries T[1..] at or below |Q| (double-float qh + ql, not necessarily normalised),
-// and h is increasing, so the signs of |Q| - T[f0] and |Q| - T[f0 + 1] settle it.  Each sign is
+// and h is increasing, so the signs of |Q| - T[f0] and |Q| - T[f0 + 1] settle it.  Entry f of the
+// table (16 bytes, 16-byte aligned) holds T[f] and T[f + 1], high then low parts.  Each sign is
 // taken from (qh - Th) + (ql - Tl): the first difference is exact whenever it is small (Sterbenz),
 // so a wrong sign needs |Q| within ~2^-24 |ql| of the boundary; |Q| itself carries the encoder's
 // error (about 2^-44 relative).  Both lie far inside the one-ulp window.
 VC_DI int table_level(int f0, float qh, float ql, const float* T, int jmax)
 {
+  typedef float f32x4_t __attribute__((vector_size(16)));
   const int f = f0 < 0 ? 0 : (f0 > jmax ? jmax : f0);
   if (T == nullptr) return f;                       // (every encoding entry point attaches them)
-  const float db = (qh - T[2 * f]) + (ql - T[2 * f + 1]);           // |Q| - (start of level f)
-  if (f > 0 && db < 0.0f) return f - 1;
-  const float dn = (qh - T[2 * f + 2]) + (ql - T[2 * f + 3]);       // |Q| - (start of level f + 1)
-  if (dn >= 0.0f) return f + 1;
-  return f;
+  const f32x4_t e = *(const f32x4_t*)(T + 4 * f);
+  const float db = (qh - e[0]) + (ql - e[1]);       // |Q| - (start of level f)
+  const float dn = (qh - e[2]) + (ql - e[3]);       // |Q| - (start of level f + 1)
+  // (|Q| cannot lie below the start of level f and at or past the start of level f + 1 at once)
+  return (f > 0 && db < 0.0f) ? f - 1 : (dn >= 0.0f ? f + 1 : f);
 }
 
 // Code of a float32 vector (the compress function of §3), single-precision arithmetic only.

@@ -4,6 +4,7 @@
 #pragma once
 
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <mutex>
@@ -214,11 +215,13 @@ static inline vc_status tanh_fits(float gamma, Params& P)
 // Level boundaries of a companded angle for the single-precision encoder: T[j] = K h^-1(j / K)
 // in the uniform level coordinate |Q| (j = 1 .. floor(K)), T[0] = 0 and a last entry past every
 // |Q|, each as a double-float pair.  h^-1 is atanh(v tanh g) / g (tanh map, R17) or
-// (2/pi) asin(v) (cosine map, R18), in long double.
-static inline void compand_boundaries(int mode, float gamma, double K, std::vector<float>& T)
+// (2/pi) asin(v) (cosine map, R18), in long double.  The table handed to the encoder holds one
+// 16-byte entry per level f (T[f] and T[f + 1], high then low parts), so that one aligned load
+// settles a level.
+static inline void compand_boundaries(int mode, float gamma, double K, std::vector<float>& Q)
 {
   const int jmax = (int)floor(K);
-  T.assign(2 * (size_t)(jmax + 2), 0.0f);
+  std::vector<float> T(2 * (size_t)(jmax + 2), 0.0f);
   const long double PI = 3.14159265358979323846264338327950288L;
   const long double g = gamma, tg = tanhl(g);
   for (int j = 1; j <= jmax; j++) {
@@ -228,6 +231,10 @@ static inline void compand_boundaries(int mode, float gamma, double K, std::vect
   }
   T[2 * (size_t)(jmax + 1)] = 3.0e38f;
   T[2 * (size_t)(jmax + 1) + 1] = 0.0f;
+  // one 16-byte entry per level f = 0 .. jmax: the boundaries at its start and at its end
+  Q.resize(4 * (size_t)(jmax + 1));
+  for (size_t f = 0; f <= (size_t)jmax; f++)
+    for (int i = 0; i < 4; i++) Q[4 * f + i] = T[2 * f + i];
 }
 
 // The boundary tables of (mode, gamma) for theta and phi of the default layout, built once per
@@ -265,8 +272,14 @@ static inline vc_status compand_tables(int mode, float gamma, const float** tt, 
   compand_boundaries(mode, gamma, ((1 << 17) - 1) / 2.0, hp);
   const float *t = nullptr, *p = nullptr;
 #ifdef VC_HOST_EMULATION
-  float* ht_own = new float[ht.size()];
-  float* hp_own = new float[hp.size()];
+  // 16-byte aligned, as the device copies (an entry is read as one 16-byte vector)
+  float* ht_own = static_cast<float*>(aligned_alloc(16, ht.size() * sizeof(float)));
+  float* hp_own = static_cast<float*>(aligned_alloc(16, hp.size() * sizeof(float)));
+  if (ht_own == nullptr || hp_own == nullptr) {
+    free(ht_own);
+    free(hp_own);
+    return VC_ERROR_OUT_OF_MEMORY;
+  }
   memcpy(ht_own, ht.data(), ht.size() * sizeof(float));
   memcpy(hp_own, hp.data(), hp.size() * sizeof(float));
   t = ht_own;
