@@ -124,7 +124,9 @@ vc_status vc_axpy(const vc_codec* c, float alpha, const uint64_t* a, const uint6
 
 /* d_out[0] = sum_i decode(a[i]) . decode(b[i]), single-precision products with
  * single-precision accumulation (fixed reduction order, deterministic).  d_out is
- * one device float. */
+ * one device float.  The paper defines no dot product of its own: this is the plain sum
+ * of products of the vectors that Eq. (a_inv) and Eq. (cart2sphere) decode.  The per-block
+ * partials go to a stream-ordered allocation (hipMallocAsync) freed before return. */
 vc_status vc_dot(const vc_codec* c, const uint64_t* a, const uint64_t* b, size_t n, float* d_out,
                  hipStream_t stream);
 
@@ -142,7 +144,8 @@ vc_status vc_dot_noalloc(const vc_codec* c, const uint64_t* a, const uint64_t* b
                          hipStream_t stream);
 
 /* d_out[0] = sum_i |decode(a[i])|^2, from the magnitude field alone (|x_hat| equals the
- * stored magnitude exactly in real arithmetic), single-precision accumulation. */
+ * stored magnitude exactly in real arithmetic), single-precision accumulation.  Like vc_dot,
+ * not a paper operation: the plain sum of squared magnitudes of the vectors of §2.3. */
 vc_status vc_norm2(const vc_codec* c, const uint64_t* a, size_t n, float* d_out, hipStream_t stream);
 
 /* Fused decode + dense apply, the operator pattern of Alg. (fr_fdiv_comp): for each
