@@ -133,6 +133,19 @@ def settle(torch, fn, ms: float = None):
         torch.cuda.synchronize()
 
 
+# codec variants of the axpy timed beside the headline codec (and launched once each by --pmc-run
+# variants): fractional split (§2.4), companding (§2.5), the truncating magnitude (§2.3), and the
+# single-precision encoder's companding (level-boundary tables)
+VARIANTS = (("frac_P2^16", {"mode": "frac", "P": 1 << 16}),
+            ("frac_P163840", {"mode": "frac", "P": 163840}),
+            ("frac_P2^18", {"mode": "frac", "P": 1 << 18}),
+            ("tanh_g0.5", {"mode": "tanh", "gamma": 0.5}),
+            ("cos", {"mode": "cos"}),
+            ("trunc_magnitude", {"mag_round": "trunc"}),
+            ("tanh_g0.5_f32encoder", {"mode": "tanh", "gamma": 0.5, "precision": "f32"}),
+            ("cos_f32encoder", {"mode": "cos", "precision": "f32"}))
+
+
 def timed(torch, fn, steps: int, warmup) -> float:
     """Average milliseconds per call of fn() (all work on torch's current stream), after `warmup`
     untimed calls, or (warmup None) untimed calls for at least SETTLE_MS."""
@@ -444,7 +457,7 @@ def main():
     ap.add_argument("--n", type=int, default=1 << 27)
     ap.add_argument("--quick", action="store_true", help="skip the side-by-side extras")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--pmc-run", nargs="?", const="axpy", default=None, choices=["axpy", "apply", "fdiv", "gather", "all"],
+    ap.add_argument("--pmc-run", nargs="?", const="axpy", default=None, choices=["axpy", "variants", "apply", "fdiv", "gather", "all"],
                     help="launch the copy kernel (counter calibration) and the selected kernels once "
                          "(axpy by default) for rocprofv3 --pmc")
     ap.add_argument("--precision", default="f64", choices=["f64", "f32"],
@@ -488,6 +501,16 @@ def main():
         if args.pmc_run in ("axpy", "all"):
             vc.vc_axpy(c, ALPHA, wa, wb, wc)
             torch.cuda.synchronize()
+        if args.pmc_run in ("variants", "all"):
+            # the headline codec with the other encoder precision, then each codec variant
+            other = "f32" if args.precision == "f64" else "f64"
+            vc.vc_axpy(vc.codec(precision=other), ALPHA, wa, wb, wc)
+            for _name, kw in VARIANTS:
+                cv = vc.codec(**dict({"precision": args.precision}, **kw))
+                va_, vb_ = vc.vc_encode(cv, a32), vc.vc_encode(cv, b32)
+                vc.vc_axpy(cv, ALPHA, va_, vb_, wc)
+                torch.cuda.synchronize()
+                del va_, vb_
         if args.pmc_run in ("apply", "all"):
             bench_apply(torch, vc, inputs, 1)
         if args.pmc_run in ("fdiv", "all"):
@@ -577,15 +600,7 @@ def main():
         log(f"axpy with {other} encoder: {ms_o:.3f} ms")
         # codec variants of the same axpy
         var = {}
-        for name, kw in (("frac_P2^16", {"mode": "frac", "P": 1 << 16}),
-                         ("frac_P163840", {"mode": "frac", "P": 163840}),
-                         ("frac_P2^18", {"mode": "frac", "P": 1 << 18}),
-                         ("tanh_g0.5", {"mode": "tanh", "gamma": 0.5}),
-                         ("cos", {"mode": "cos"}),
-                         ("trunc_magnitude", {"mag_round": "trunc"}),
-                         # the single-precision encoder's companding (level-boundary tables)
-                         ("tanh_g0.5_f32encoder", {"mode": "tanh", "gamma": 0.5, "precision": "f32"}),
-                         ("cos_f32encoder", {"mode": "cos", "precision": "f32"})):
+        for name, kw in VARIANTS:
             kw = dict({"precision": args.precision}, **kw)
             cv = vc.codec(**kw)
             va_ = vc.vc_encode(cv, a32)
